@@ -1,0 +1,206 @@
+"""Benchmark: blocked Floyd-Warshall APSP on one MI355X.
+
+Default workload: one directed graph, n = 32768, edge probability 0.8, int32
+weights uniform on [1, 10000], "no edge" = 2^30, distances + successor
+matrix (the headline configuration).  One step = restore the input into the
+working matrix (device-to-device copy) + one full solve (input
+normalisation and every round's three phases).  The metric is n^3
+relaxations per second (one relaxation = one (k, i, j) triple of the
+Floyd-Warshall loop; the paper's GFLOPS = 2 n^3 / t counts two operations per
+relaxation).
+
+Prints one JSON line.  Besides the driver's fields it carries
+  roofline     : the phase-3 (min-plus) kernel, timed live with HIP events on
+                 the solver's stream, against the MI355X VALU lane-op peak;
+  cpu_baseline : the CPU oracle (plain triple loop) timed on this host on a
+                 bounded sample of the same recipe.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 64 VALU lanes x 2.4 GHz peak engine clock
+VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# fewest VALU lane-ops one min-plus relaxation needs on CDNA4: one 32-bit add
+# plus half of a three-input min (v_min3 folds two candidates into the running
+# minimum)
+OPS_PER_RELAX = 1.5
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("fw_kernels.hip", "fw_internal.h"):
+        with open(os.path.join(ROOT, "paper_2403_18619_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload_key: str, per_launch_bytes_alg: float):
+    """HBM traffic of the phase-3 kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "phase3_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    ent = rec.get(workload_key)
+    if not ent or ent.get("kernel_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def phase3_relaxations(n: int, bs: int) -> int:
+    """Relaxations done by all phase-3 launches of one solve: round K updates
+    the (n - bk)^2 entries outside its band with bk k's each."""
+    tot = 0
+    for K in range((n + bs - 1) // bs):
+        bk = min(bs, n - K * bs)
+        tot += (n - bk) * (n - bk) * bk
+    return tot
+
+
+def cpu_baseline(args):
+    import oracle
+    import synth
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    m = args.cpu_n
+    if args.dtype == "i32":
+        W = synth.graph_i32(m, args.seed, args.p, args.lo, args.hi)
+        fn = oracle.fw_i32
+    else:
+        W = synth.graph_f32(m, args.seed, args.p, args.lo, args.hi)
+        fn = oracle.fw_f32
+    log(f"cpu baseline: oracle on n={m}, {threads} threads")
+    t0 = time.perf_counter()
+    fn(W, next_hop=not args.no_next, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": m ** 3 / dt, "unit": "relaxations/s", "cores": threads, "kind": "oracle",
+            "sample": (f"plain triple-loop oracle, one full solve of the same recipe at n={m} "
+                       f"(seed {args.seed}), {'dist+next' if not args.no_next else 'dist'}, "
+                       f"{dt:.2f} s; rate scales as n^3 work"),
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=32768)
+    ap.add_argument("--dtype", choices=["i32", "f32"], default="i32")
+    ap.add_argument("--p", type=float, default=0.8)
+    ap.add_argument("--lo", type=float, default=1)
+    ap.add_argument("--hi", type=float, default=10000)
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--no-next", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=4096)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "row-strip design is described but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2403_18619_amd as fw
+
+    n = args.n
+    log(f"generating n={n} {args.dtype} graph (p={args.p}, U[{args.lo},{args.hi}], seed {args.seed})")
+    if args.dtype == "i32":
+        W = synth.graph_i32(n, args.seed, args.p, int(args.lo), int(args.hi))
+    else:
+        W = synth.graph_f32(n, args.seed, args.p, args.lo, args.hi)
+    dev = torch.device("cuda:0")
+    Wd = torch.from_numpy(W).to(dev)
+    del W
+    D = torch.empty_like(Wd)
+    NX = None if args.no_next else torch.empty((n, n), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    bs = args.block or 128
+
+    def step(flags):
+        D.copy_(Wd)
+        fw.solve_(D, NX, block=args.block, schedule=args.schedule, flags=flags, stream=stream)
+
+    log(f"warmup x{args.warmup}")
+    for _ in range(args.warmup):
+        step(0)
+    torch.cuda.synchronize()
+    fw.check()
+    fw.phase_times()
+
+    log(f"timing x{args.steps}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(fw.FLAG_TIME_PHASES)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fw.check()
+    ph = fw.phase_times()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = n ** 3 / (ms_per_step / 1e3)
+    log(f"{ms_per_step:.1f} ms/step, {value:.4g} relaxations/s")
+
+    # dominant kernel: phase 3 (or the persistent kernel)
+    kind = "persistent" if ph["persistent"][1] else "phase3"
+    k_ms, k_launches = ph[kind]
+    relax_per_solve = phase3_relaxations(n, bs) if kind == "phase3" else n ** 3
+    relax_per_launch = relax_per_solve / (k_launches / args.steps)
+    avg_s = k_ms / k_launches / 1e3
+    achieved = OPS_PER_RELAX * relax_per_launch / avg_s
+    esz = 4
+    alg_bytes = None
+    traffic = load_traffic(f"{args.dtype}_n{n}_bs{bs}_{'next' if NX is not None else 'dist'}", alg_bytes)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
+                "unit": "Top/s", "frac": achieved / VALU_PEAK_LANE_OPS, "traffic": traffic,
+                "kernel": kind, "avg_launch_ms": avg_s * 1e3, "launches_per_step": k_launches / args.steps,
+                "ops_per_relaxation": OPS_PER_RELAX}
+    phase_ms = {k: (v[0] / args.steps) for k, v in ph.items() if v[1]}
+    del esz
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args)
+
+    wl = (f"blocked FW, one directed graph n={n}, edge prob {args.p}, "
+          f"{'int32' if args.dtype == 'i32' else 'float32'} weights U[{args.lo:g},{args.hi:g}]"
+          f"{', INF 2^30' if args.dtype == 'i32' else ''}, "
+          f"{'dist + int32 next-hop' if NX is not None else 'dist only'}")
+    out = {
+        "metric": "n^3 relaxations/s, blocked FW n=32768; batched + fwd/bwd vs plain, 1 GPU",
+        "value": value, "unit": "relaxations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32" if args.dtype == "i32" else "f32",
+        "data": "synthetic (seeded counter-based generator)",
+        "config": {"workload": wl, "n": n, "block": bs,
+                   "schedule": {0: "auto", 1: "three-launch", 2: "persistent"}[args.schedule],
+                   "next_hop": NX is not None, "seed": args.seed},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "phase_ms_per_step": phase_ms,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

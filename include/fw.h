@@ -1,0 +1,119 @@
+/*
+ * fw.h -- C ABI of the MI355X (gfx950) blocked Floyd-Warshall solver.
+ *
+ * The operation is all-pairs shortest paths by blocked Floyd-Warshall
+ * (Calderon, Rucci, Chichizola, "Enhanced OpenMP Algorithm to Compute
+ * All-Pairs Shortest Path on x86 Architectures", Section 2.3): the input is a
+ * dense n x n matrix whose entry (i, j) is the weight of edge i -> j, or
+ * "infinite" for no edge; the output replaces it, in place, by the length of
+ * a shortest path from i to j, and a second matrix records the paths.
+ * Section 2.3 lists a reusable library for third-party C/C++ programs as the
+ * paper's future work; this header is that library's interface.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All matrix pointers are DEVICE pointers owned by the caller; they must
+ *    stay valid until the work enqueued on `stream` has finished.  `stream`
+ *    is a hipStream_t passed as void* (NULL = the default stream).  Work is
+ *    enqueued asynchronously; a return of FW_OK means "enqueued".
+ *  - Row-major storage with leading dimension `ld` (elements, ld >= n); the
+ *    distance and next-hop matrices share `ld`.
+ *  - int32 weights: an entry >= FW_INF_I32 (2^30) means "no edge" and is
+ *    rewritten to FW_INF_I32.  Finite shortest-path lengths must stay below
+ *    2^30.  float32 weights: +INFINITY means "no edge".  Weights must be
+ *    >= 0 (no NaN); the diagonal is forced to 0 (self-loops are ignored).
+ *  - next (may be NULL: distances only) receives the successor matrix:
+ *    next[i][j] is the vertex after i on the chosen shortest path from i to
+ *    j, next[i][i] = i, next[i][j] = -1 when j is unreachable.  (The paper's
+ *    path matrix P stores the last intermediate vertex instead; a successor
+ *    matrix walks a path in order.)  Where several shortest paths tie, any
+ *    valid successor matrix may be returned; for a given input, block size
+ *    and data type every schedule returns the same bits.
+ *  - Argument errors are detected on the host and returned before anything
+ *    is enqueued; the text is then available from fw_last_error().  Errors
+ *    found by the device (validate mode, dependency-wait timeout) are
+ *    reported by fw_check().  After an error the output contents are
+ *    unspecified.
+ *  - n == 0 is a valid no-op.  Thread safety: calls from several host threads
+ *    are allowed; calls that overlap on the same device share one small
+ *    per-device workspace (error word, schedule counters), so concurrent
+ *    solves on different streams of one device must be serialised by the
+ *    caller.
+ */
+#ifndef FWGPU_FW_H
+#define FWGPU_FW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fw_status {
+    FW_OK = 0,
+    FW_ERR_INVALID_ARG = -1,   /* bad pointer, size, ld or option           */
+    FW_ERR_UNSUPPORTED = -2,   /* valid request this build cannot run       */
+    FW_ERR_HIP = -3,           /* a HIP runtime call failed (see last error) */
+    FW_ERR_NEGATIVE = -4,      /* validate mode: negative or NaN weight      */
+    FW_ERR_TIMEOUT = -5        /* persistent schedule: a wait hit its bound  */
+} fw_status;
+
+#define FW_INF_I32 1073741824   /* 2^30: int32 "no edge" and unreachable */
+
+/* Schedules (fw_options.schedule). */
+#define FW_SCHED_AUTO 0         /* library's choice                          */
+#define FW_SCHED_THREE_LAUNCH 1 /* per round: phase 1, phase 2, phase 3      */
+#define FW_SCHED_PERSISTENT 2   /* one launch, per-tile dependency flags     */
+
+typedef struct fw_options {
+    int32_t block;     /* block size BS (k-depth of one round): 0 = auto, or 32, 64, 128 */
+    int32_t schedule;  /* FW_SCHED_*                                      */
+    int32_t validate;  /* non-zero: the device checks every weight (>= 0,
+                          not NaN) and fw_check() reports FW_ERR_NEGATIVE  */
+    int32_t flags;     /* 0, or FW_FLAG_TIME_PHASES                        */
+} fw_options;
+
+/* fw_options.flags: record a pair of HIP events on the solve's stream around
+ * every kernel launch and accumulate their durations per phase (read with
+ * fw_phase_times).  The events are stream markers; the kernels are unchanged. */
+#define FW_FLAG_TIME_PHASES 1
+
+/* Solve in place (Section 2.3, blocked form with block size BS).
+ *   dist : n x n (storage n x ld) int32 / float32 weights in, distances out.
+ *   next : n x n (storage n x ld) int32 successor matrix out, or NULL.
+ *   n    : number of vertices, 0 <= n < 2^31 - 1.
+ *   ld   : leading dimension of dist and next, in elements, ld >= max(n, 1).
+ * The _ex forms take options (NULL = defaults). */
+fw_status fw_solve_i32(int32_t *dist, int32_t *next, int64_t n, int64_t ld, void *stream);
+fw_status fw_solve_f32(float *dist, int32_t *next, int64_t n, int64_t ld, void *stream);
+fw_status fw_solve_ex_i32(int32_t *dist, int32_t *next, int64_t n, int64_t ld,
+                          const fw_options *opt, void *stream);
+fw_status fw_solve_ex_f32(float *dist, int32_t *next, int64_t n, int64_t ld,
+                          const fw_options *opt, void *stream);
+
+/* Waits for `stream`, then returns (and clears) the first error the device
+ * recorded for the current device since the last fw_check: FW_ERR_NEGATIVE,
+ * FW_ERR_TIMEOUT, or FW_OK. */
+fw_status fw_check(void *stream);
+
+/* Kernel time accumulated by solves run with FW_FLAG_TIME_PHASES since the
+ * previous call, per kind of launch: index 0 input normalisation, 1 phase 1,
+ * 2 phase 2, 3 phase 3, 4 persistent (whole solve).  Waits for the recorded
+ * events, writes total milliseconds to ms[0..4] and launch counts to
+ * launches[0..4] (host pointers, either may be NULL), then resets. */
+fw_status fw_phase_times(double *ms, int64_t *launches);
+
+/* Static description of a status code. */
+const char *fw_status_string(int status);
+
+/* Detail text of the last error returned on the calling host thread. */
+const char *fw_last_error(void);
+
+/* ABI version: (major << 16) | minor. */
+int32_t fw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FWGPU_FW_H */

@@ -1,0 +1,168 @@
+"""ctypes binding of libfwgpu.so: argument marshalling only.
+
+Every step of a solve runs in the library's HIP kernels; torch provides the
+device memory and the stream.  There is no fallback: if the library is not
+built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfwgpu.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "fw.h")
+
+FW_OK = 0
+FW_ERR_INVALID_ARG = -1
+FW_ERR_UNSUPPORTED = -2
+FW_ERR_HIP = -3
+FW_ERR_NEGATIVE = -4
+FW_ERR_TIMEOUT = -5
+FW_INF_I32 = 1 << 30
+
+SCHED_AUTO, SCHED_THREE_LAUNCH, SCHED_PERSISTENT = 0, 1, 2
+FLAG_TIME_PHASES = 1
+PHASE_KINDS = ("init", "phase1", "phase2", "phase3", "persistent")
+
+
+class fw_options(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("validate", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class FwError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{status_string(status)} ({detail})" if detail else status_string(status))
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python paper_2403_18619_amd/build.py` "
+                          "(hipcc, gfx950); there is no CPU fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    opt_p = ctypes.POINTER(fw_options)
+    for name in ("fw_solve_i32", "fw_solve_f32"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, vp, i64, i64, vp]
+        f.restype = i32
+    for name in ("fw_solve_ex_i32", "fw_solve_ex_f32"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, vp, i64, i64, opt_p, vp]
+        f.restype = i32
+    lib.fw_check.argtypes = [vp]
+    lib.fw_check.restype = i32
+    lib.fw_status_string.argtypes = [ctypes.c_int]
+    lib.fw_status_string.restype = ctypes.c_char_p
+    lib.fw_last_error.argtypes = []
+    lib.fw_last_error.restype = ctypes.c_char_p
+    lib.fw_phase_times.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.fw_phase_times.restype = i32
+    lib.fw_version.argtypes = []
+    lib.fw_version.restype = i32
+    return lib
+
+
+lib = _load()
+
+
+def status_string(status: int) -> str:
+    return lib.fw_status_string(status).decode()
+
+
+def last_error() -> str:
+    return lib.fw_last_error().decode()
+
+
+def _raise_if(status: int):
+    if status != FW_OK:
+        raise FwError(status, last_error())
+
+
+def header_symbols(path: str = HEADER):
+    """Names of every function the C header declares."""
+    text = open(path).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(fw_\w+)\s*\(", text, re.M)))
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_matrix(t, name):
+    import torch
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device (cuda/hip) tensor")
+    if t.dim() != 2 or t.shape[0] != t.shape[1]:
+        raise ValueError(f"{name} must be a square matrix, got shape {tuple(t.shape)}")
+    n = t.shape[0]
+    if n and (t.stride(1) != 1 or t.stride(0) < n):
+        raise ValueError(f"{name} must be row-major with unit column stride and row stride >= n")
+    return n, (t.stride(0) if n else 1)
+
+
+def solve_(dist, next=None, *, block: int = 0, schedule: int = 0, validate: bool = False,
+           stream=None, flags: int = 0):
+    """In-place solve of ``dist`` (n x n view of an n x ld row-major matrix).
+
+    ``next``: None (distances only) or an int32 tensor with the same shape and
+    strides as ``dist``; receives the successor matrix."""
+    import torch
+    n, ld = _check_matrix(dist, "dist")
+    if dist.dtype == torch.int32:
+        fn = lib.fw_solve_ex_i32
+    elif dist.dtype == torch.float32:
+        fn = lib.fw_solve_ex_f32
+    else:
+        raise ValueError(f"dist dtype {dist.dtype} is not supported (int32 or float32)")
+    nptr = None
+    if next is not None:
+        if next.dtype != torch.int32 or next.shape != dist.shape or (n and next.stride() != dist.stride()):
+            raise ValueError("next must be int32 with the same shape and strides as dist")
+        if next.device != dist.device:
+            raise ValueError("next must be on the same device as dist")
+        nptr = next.data_ptr()
+    opt = fw_options(block, schedule, 1 if validate else 0, flags)
+    with torch.cuda.device(dist.device):
+        st = fn(dist.data_ptr(), nptr, n, ld, ctypes.byref(opt), _stream_handle(stream))
+    _raise_if(st)
+    return dist, next
+
+
+def solve(W, next_hop: bool = True, *, block: int = 0, schedule: int = 0,
+          validate: bool = False, stream=None):
+    """Out-of-place solve: returns (D, NX) (NX is None when next_hop is False).
+
+    W: square int32 or float32 device tensor of edge weights (int32: >= 2^30
+    = no edge; float32: +inf = no edge)."""
+    import torch
+    n, ld = _check_matrix(W, "W")
+    D = torch.empty((n, ld), dtype=W.dtype, device=W.device)[:, :n]
+    D.copy_(W)
+    NX = torch.empty((n, ld), dtype=torch.int32, device=W.device)[:, :n] if next_hop else None
+    solve_(D, NX, block=block, schedule=schedule, validate=validate, stream=stream)
+    return D, NX
+
+
+def check(stream=None):
+    """Wait for the stream and raise the first device-side error, if any."""
+    _raise_if(lib.fw_check(_stream_handle(stream)))
+
+
+def phase_times():
+    """{kind: (total_ms, launches)} accumulated by solves run with
+    flags=FLAG_TIME_PHASES since the previous call (waits for them)."""
+    ms = (ctypes.c_double * 5)()
+    cnt = (ctypes.c_int64 * 5)()
+    _raise_if(lib.fw_phase_times(ms, cnt))
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(PHASE_KINDS)}
+
+
+def version() -> int:
+    return int(lib.fw_version())

@@ -1,0 +1,239 @@
+// C ABI of the blocked Floyd-Warshall solver: argument checks, the plan
+// (block size, schedule), the per-device workspace and the launch sequence.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "fw.h"
+#include "fw_internal.h"
+
+namespace {
+
+thread_local char g_err[512];
+
+fw_status fail(fw_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+fw_status hip_fail(hipError_t e, const char *what) {
+    return fail(FW_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+std::mutex g_mu;
+std::unordered_map<int, fw::DeviceWork> g_work;
+
+// The per-device workspace is allocated on first use and kept until exit.
+fw_status get_work(fw::DeviceWork **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_mu);
+    fw::DeviceWork &w = g_work[dev];
+    if (!w.err) {
+        e = hipMalloc(&w.err, 256);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
+        e = hipMemset(w.err, 0, 256);
+        if (e != hipSuccess) return hip_fail(e, "hipMemset(workspace)");
+    }
+    *out = &w;
+    return FW_OK;
+}
+
+fw_status check_args(const void *dist, int64_t n, int64_t ld, const fw_options *opt) {
+    if (n < 0) return fail(FW_ERR_INVALID_ARG, "n = %lld is negative", (long long)n);
+    if (n >= (int64_t)INT32_MAX) return fail(FW_ERR_INVALID_ARG, "n = %lld does not fit the int32 successor matrix", (long long)n);
+    if (n == 0) return FW_OK;
+    if (!dist) return fail(FW_ERR_INVALID_ARG, "dist is NULL");
+    if (ld < n) return fail(FW_ERR_INVALID_ARG, "ld = %lld < n = %lld", (long long)ld, (long long)n);
+    if (ld > INT64_MAX / 4 / n) return fail(FW_ERR_INVALID_ARG, "n * ld overflows");
+    if (opt) {
+        if (opt->block != 0 && opt->block != 32 && opt->block != 64 && opt->block != 128)
+            return fail(FW_ERR_INVALID_ARG, "block = %d (allowed: 0, 32, 64, 128)", opt->block);
+        if (opt->schedule < FW_SCHED_AUTO || opt->schedule > FW_SCHED_PERSISTENT)
+            return fail(FW_ERR_INVALID_ARG, "schedule = %d", opt->schedule);
+        if (opt->flags & ~FW_FLAG_TIME_PHASES) return fail(FW_ERR_INVALID_ARG, "flags = %d (unknown bits)", opt->flags);
+    }
+    return FW_OK;
+}
+
+// ---- optional per-phase timing (FW_FLAG_TIME_PHASES)
+constexpr int kKinds = 5;
+struct Timing {
+    std::mutex mu;
+    std::vector<hipEvent_t> free_events;
+    struct Pending { int kind; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+};
+Timing g_timing;
+
+hipError_t take_event(hipEvent_t *ev) {
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    if (!g_timing.free_events.empty()) {
+        *ev = g_timing.free_events.back();
+        g_timing.free_events.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(ev);
+}
+
+// Launch `fn` between two events when timing is on.
+template <typename F>
+hipError_t timed(bool on, int kind, hipStream_t st, F fn) {
+    if (!on) return fn();
+    hipEvent_t a, b;
+    hipError_t e = take_event(&a);
+    if (e != hipSuccess) return e;
+    e = take_event(&b);
+    if (e != hipSuccess) return e;
+    if ((e = hipEventRecord(a, st)) != hipSuccess) return e;
+    if ((e = fn()) != hipSuccess) return e;
+    if ((e = hipEventRecord(b, st)) != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    g_timing.pending.push_back({kind, a, b});
+    return hipSuccess;
+}
+
+int auto_block(int64_t n) {
+    if (n <= 32) return 32;
+    if (n <= 64) return 64;
+    return 128;
+}
+
+fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
+                const fw_options *opt, void *stream) {
+    g_err[0] = 0;
+    fw_status s = check_args(dist, n, ld, opt);
+    if (s != FW_OK || n == 0) return s;
+    fw_options o = {0, FW_SCHED_AUTO, 0, 0};
+    if (opt) o = *opt;
+    if (o.schedule == FW_SCHED_PERSISTENT)
+        return fail(FW_ERR_UNSUPPORTED, "persistent schedule is not available in this build");
+
+    fw::Plan p;
+    p.dtype = dt;
+    p.dist = dist;
+    p.next = next;
+    p.n = n;
+    p.ld = ld;
+    p.bs = o.block ? o.block : auto_block(n);
+    p.rounds = (int)((n + p.bs - 1) / p.bs);
+    p.nt = (int)((n + fw::kTile - 1) / fw::kTile);
+    p.vec = (ld % 4 == 0) && ((uintptr_t)dist % 16 == 0);
+    p.validate = o.validate != 0;
+    p.stream = (hipStream_t)stream;
+    s = get_work(&p.work);
+    if (s != FW_OK) return s;
+
+    const bool tm = (o.flags & FW_FLAG_TIME_PHASES) != 0;
+    hipError_t e = timed(tm, 0, p.stream, [&] { return fw::launch_init(p); });
+    if (e != hipSuccess) return hip_fail(e, "init launch");
+    for (int K = 0; K < p.rounds; ++K) {
+        e = timed(tm, 1, p.stream, [&] { return fw::launch_phase1(p, K); });
+        if (e != hipSuccess) return hip_fail(e, "phase 1 launch");
+        if (p.rounds == 1) break;
+        e = timed(tm, 2, p.stream, [&] { return fw::launch_phase2(p, K); });
+        if (e != hipSuccess) return hip_fail(e, "phase 2 launch");
+        e = timed(tm, 3, p.stream, [&] { return fw::launch_phase3(p, K); });
+        if (e != hipSuccess) return hip_fail(e, "phase 3 launch");
+    }
+    return FW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fw_status fw_solve_i32(int32_t *dist, int32_t *next, int64_t n, int64_t ld, void *stream) {
+    return solve(fw::DType::I32, dist, next, n, ld, nullptr, stream);
+}
+
+fw_status fw_solve_f32(float *dist, int32_t *next, int64_t n, int64_t ld, void *stream) {
+    return solve(fw::DType::F32, dist, next, n, ld, nullptr, stream);
+}
+
+fw_status fw_solve_ex_i32(int32_t *dist, int32_t *next, int64_t n, int64_t ld,
+                          const fw_options *opt, void *stream) {
+    return solve(fw::DType::I32, dist, next, n, ld, opt, stream);
+}
+
+fw_status fw_solve_ex_f32(float *dist, int32_t *next, int64_t n, int64_t ld,
+                          const fw_options *opt, void *stream) {
+    return solve(fw::DType::F32, dist, next, n, ld, opt, stream);
+}
+
+fw_status fw_check(void *stream) {
+    g_err[0] = 0;
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    fw::DeviceWork *w = nullptr;
+    fw_status s = get_work(&w);
+    if (s != FW_OK) return s;
+    int code = 0;
+    e = hipMemcpy(&code, w->err, sizeof code, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(error word)");
+    if (code == 0) return FW_OK;
+    e = hipMemset(w->err, 0, sizeof code);
+    if (e != hipSuccess) return hip_fail(e, "hipMemset(error word)");
+    if (code == 1) return fail(FW_ERR_NEGATIVE, "a weight is negative or NaN");
+    if (code == 2) return fail(FW_ERR_TIMEOUT, "a dependency wait exceeded its bound");
+    return fail(FW_ERR_HIP, "device error word %d", code);
+}
+
+fw_status fw_phase_times(double *ms, int64_t *launches) {
+    g_err[0] = 0;
+    std::vector<Timing::Pending> todo;
+    {
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        todo.swap(g_timing.pending);
+    }
+    double acc[kKinds] = {0, 0, 0, 0, 0};
+    int64_t cnt[kKinds] = {0, 0, 0, 0, 0};
+    fw_status st = FW_OK;
+    for (auto &pe : todo) {
+        if (st == FW_OK) {
+            hipError_t e = hipEventSynchronize(pe.b);
+            float t = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, pe.a, pe.b);
+            if (e != hipSuccess) {
+                st = hip_fail(e, "phase timing events");
+            } else {
+                acc[pe.kind] += t;
+                cnt[pe.kind] += 1;
+            }
+        }
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        g_timing.free_events.push_back(pe.a);
+        g_timing.free_events.push_back(pe.b);
+    }
+    for (int k = 0; k < kKinds; ++k) {
+        if (ms) ms[k] = acc[k];
+        if (launches) launches[k] = cnt[k];
+    }
+    return st;
+}
+
+const char *fw_status_string(int status) {
+    switch (status) {
+    case FW_OK: return "FW_OK";
+    case FW_ERR_INVALID_ARG: return "FW_ERR_INVALID_ARG: invalid argument";
+    case FW_ERR_UNSUPPORTED: return "FW_ERR_UNSUPPORTED: unsupported request";
+    case FW_ERR_HIP: return "FW_ERR_HIP: HIP runtime error";
+    case FW_ERR_NEGATIVE: return "FW_ERR_NEGATIVE: negative or NaN weight";
+    case FW_ERR_TIMEOUT: return "FW_ERR_TIMEOUT: dependency wait timed out";
+    default: return "unknown status";
+    }
+}
+
+const char *fw_last_error(void) { return g_err; }
+
+int32_t fw_version(void) { return (1 << 16) | 0; }
+
+}  // extern "C"

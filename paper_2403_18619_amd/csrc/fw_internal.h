@@ -1,0 +1,39 @@
+// Internal interface between the host dispatcher and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fw {
+
+constexpr int kTile = 128;     // output tile edge of the min-plus kernel
+constexpr int kThreads = 256;  // threads per workgroup (four wave64s)
+
+enum class DType { I32, F32 };
+
+// Per-device scratch owned by the library (a few words).
+struct DeviceWork {
+    int *err = nullptr;        // device error word (0 = none)
+};
+
+struct Plan {
+    DType dtype;
+    void *dist;
+    int32_t *next;             // may be null
+    int64_t n, ld;
+    int bs;                    // block size (k-depth of a round)
+    int rounds;                // ceil(n / bs)
+    int nt;                    // ceil(n / kTile)
+    bool vec;                  // 16-byte global accesses are legal
+    bool validate;
+    hipStream_t stream;
+    DeviceWork *work;
+};
+
+// Enqueue helpers (fw_kernels.hip).  Each returns the launch's hipError_t.
+hipError_t launch_init(const Plan &p);
+hipError_t launch_phase1(const Plan &p, int K);
+hipError_t launch_phase2(const Plan &p, int K);
+hipError_t launch_phase3(const Plan &p, int K);
+
+}  // namespace fw

@@ -1,0 +1,57 @@
+"""The C-ABI library loads, exports every declared symbol and rejects bad
+arguments on the host before touching the GPU (no GPU needed)."""
+import ctypes
+
+import pytest
+
+import paper_2403_18619_amd as fw
+from paper_2403_18619_amd import _binding as B
+
+
+def test_exports_every_header_symbol():
+    syms = fw.header_symbols()
+    assert {"fw_solve_i32", "fw_solve_f32", "fw_solve_ex_i32", "fw_solve_ex_f32",
+            "fw_check", "fw_status_string", "fw_last_error", "fw_version",
+            "fw_phase_times"} <= set(syms)
+    raw = ctypes.CDLL(fw.LIB_PATH)
+    for s in syms:
+        assert hasattr(raw, s), f"{s} declared in fw.h but not exported"
+
+
+def test_version_and_status_strings():
+    assert fw.version() >> 16 == 1
+    for code in (0, -1, -2, -3, -4, -5):
+        assert fw.status_string(code).startswith("FW_")
+    assert fw.status_string(42) == "unknown status"
+
+
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: every case fails its host check
+
+
+@pytest.mark.parametrize("fn", ["fw_solve_i32", "fw_solve_f32"])
+def test_invalid_arguments_rejected_on_host(fn):
+    f = getattr(fw.lib, fn)
+    assert f(FAKE, None, -1, 4, None) == fw.FW_ERR_INVALID_ARG
+    assert "negative" in fw.last_error()
+    assert f(None, None, 4, 4, None) == fw.FW_ERR_INVALID_ARG
+    assert "NULL" in fw.last_error()
+    assert f(FAKE, None, 8, 7, None) == fw.FW_ERR_INVALID_ARG
+    assert "ld" in fw.last_error()
+    assert f(FAKE, None, 1 << 31, 1 << 31, None) == fw.FW_ERR_INVALID_ARG
+    assert f(FAKE, None, 1 << 30, 1 << 60, None) == fw.FW_ERR_INVALID_ARG
+    assert f(None, None, 0, 0, None) == fw.FW_OK          # empty problem: a no-op
+
+
+@pytest.mark.parametrize("fn", ["fw_solve_ex_i32", "fw_solve_ex_f32"])
+def test_invalid_options_rejected_on_host(fn):
+    f = getattr(fw.lib, fn)
+    for opt in (B.fw_options(48, 0, 0, 0), B.fw_options(256, 0, 0, 0), B.fw_options(0, 7, 0, 0),
+                B.fw_options(0, -1, 0, 0), B.fw_options(0, 0, 0, 2)):
+        assert f(FAKE, None, 16, 16, ctypes.byref(opt), None) == fw.FW_ERR_INVALID_ARG
+        assert fw.last_error()
+
+
+def test_python_binding_rejects_host_tensors():
+    torch = pytest.importorskip("torch")
+    with pytest.raises(ValueError):
+        fw.solve(torch.zeros(4, 4, dtype=torch.int32))
