@@ -70,13 +70,17 @@ typedef struct fw_options {
     int32_t schedule;  /* FW_SCHED_*                                      */
     int32_t validate;  /* non-zero: the device checks every weight (>= 0,
                           not NaN) and fw_check() reports FW_ERR_NEGATIVE  */
-    int32_t flags;     /* 0, or FW_FLAG_TIME_PHASES                        */
+    int32_t flags;     /* 0, or FW_FLAG_* bits below                       */
 } fw_options;
 
 /* fw_options.flags: record a pair of HIP events on the solve's stream around
  * every kernel launch and accumulate their durations per phase (read with
  * fw_phase_times).  The events are stream markers; the kernels are unchanged. */
 #define FW_FLAG_TIME_PHASES 1
+/* fw_options.flags: reference variant of the successor bookkeeping that
+ * compares and records k at every relaxation (about 2.5x slower).  It selects
+ * the same successors as the default, bit for bit; tests use it as a check. */
+#define FW_FLAG_EAGER_ARGMIN 2
 
 /* Solve in place (Section 2.3, blocked form with block size BS).
  *   dist : n x n (storage n x ld) int32 / float32 weights in, distances out.

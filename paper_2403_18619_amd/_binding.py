@@ -24,6 +24,7 @@ FW_INF_I32 = 1 << 30
 
 SCHED_AUTO, SCHED_THREE_LAUNCH, SCHED_PERSISTENT = 0, 1, 2
 FLAG_TIME_PHASES = 1
+FLAG_EAGER_ARGMIN = 2
 PHASE_KINDS = ("init", "phase1", "phase2", "phase3", "persistent")
 
 
@@ -136,7 +137,7 @@ def solve_(dist, next=None, *, block: int = 0, schedule: int = 0, validate: bool
 
 
 def solve(W, next_hop: bool = True, *, block: int = 0, schedule: int = 0,
-          validate: bool = False, stream=None):
+          validate: bool = False, stream=None, flags: int = 0):
     """Out-of-place solve: returns (D, NX) (NX is None when next_hop is False).
 
     W: square int32 or float32 device tensor of edge weights (int32: >= 2^30
@@ -146,7 +147,7 @@ def solve(W, next_hop: bool = True, *, block: int = 0, schedule: int = 0,
     D = torch.empty((n, ld), dtype=W.dtype, device=W.device)[:, :n]
     D.copy_(W)
     NX = torch.empty((n, ld), dtype=torch.int32, device=W.device)[:, :n] if next_hop else None
-    solve_(D, NX, block=block, schedule=schedule, validate=validate, stream=stream)
+    solve_(D, NX, block=block, schedule=schedule, validate=validate, stream=stream, flags=flags)
     return D, NX
 
 

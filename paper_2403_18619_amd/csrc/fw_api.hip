@@ -59,7 +59,7 @@ fw_status check_args(const void *dist, int64_t n, int64_t ld, const fw_options *
             return fail(FW_ERR_INVALID_ARG, "block = %d (allowed: 0, 32, 64, 128)", opt->block);
         if (opt->schedule < FW_SCHED_AUTO || opt->schedule > FW_SCHED_PERSISTENT)
             return fail(FW_ERR_INVALID_ARG, "schedule = %d", opt->schedule);
-        if (opt->flags & ~FW_FLAG_TIME_PHASES) return fail(FW_ERR_INVALID_ARG, "flags = %d (unknown bits)", opt->flags);
+        if (opt->flags & ~(FW_FLAG_TIME_PHASES | FW_FLAG_EAGER_ARGMIN)) return fail(FW_ERR_INVALID_ARG, "flags = %d (unknown bits)", opt->flags);
     }
     return FW_OK;
 }
@@ -128,6 +128,7 @@ fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
     p.nt = (int)((n + fw::kTile - 1) / fw::kTile);
     p.vec = (ld % 4 == 0) && ((uintptr_t)dist % 16 == 0);
     p.validate = o.validate != 0;
+    p.eager_argmin = (o.flags & FW_FLAG_EAGER_ARGMIN) != 0;
     p.stream = (hipStream_t)stream;
     s = get_work(&p.work);
     if (s != FW_OK) return s;

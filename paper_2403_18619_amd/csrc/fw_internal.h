@@ -26,6 +26,7 @@ struct Plan {
     int nt;                    // ceil(n / kTile)
     bool vec;                  // 16-byte global accesses are legal
     bool validate;
+    bool eager_argmin;         // successor variant: per-relaxation tracking
     hipStream_t stream;
     DeviceWork *work;
 };

@@ -193,17 +193,25 @@ __global__ __launch_bounds__(256) void phase1_kernel(U *__restrict__ D, int32_t 
 }
 
 // ---------------------------------------------------- phases 2 and 3
-// Thread (tx, ty) of the 16 x 16 grid owns an 8 x 8 patch of the 128 x 128
-// output tile: rows ty*4 + {0..3} and 64 + ty*4 + {0..3}, columns likewise
-// with tx, so that every LDS read of four consecutive entries is one 16-byte
-// access and a wave's global row accesses are 256 contiguous bytes.
-__device__ __forceinline__ int patch_off(int q, int r) { return (r < 4) ? q * 4 + r : 64 + q * 4 + (r - 4); }
+// Geometry of the 128 x 128 output tile.  Thread (tx, ty) of a TXN x 16 grid
+// owns 8 rows -- ty*4 + {0..3} and 64 + ty*4 + {0..3} -- and CPT columns --
+// tx*4 + {0..3}, plus 64 + tx*4 + {0..3} when CPT = 8 -- so that each LDS read
+// of four consecutive entries is one 16-byte access and a wave's global row
+// accesses are contiguous runs of at least 256 bytes.
+template <int NT> struct Geo {
+    static constexpr int threads = NT;
+    static constexpr int cpt = (NT == 512) ? 4 : 8;     // columns per thread
+    static constexpr int txn = kTile / cpt;             // threads along a row
+    static constexpr int waves = NT / 64;
+    static __device__ __forceinline__ int row_off(int ty, int r) { return (r >> 2) * 64 + ty * 4 + (r & 3); }
+    static __device__ __forceinline__ int col_off(int tx, int c) { return (c >> 2) * (txn * 4) + tx * 4 + (c & 3); }
+};
 
 template <typename U>
 __device__ __forceinline__ void load_row4(const U *__restrict__ p, int64_t col, int lim_valid,
                                           bool vec, U out[4]) {
-    // entries p[col .. col+3]; entry e exists iff (local index + e) < lim_valid,
-    // where col's local index is folded into lim_valid by the caller.
+    // entries p[col .. col+3]; entry e exists iff e < lim_valid (the caller
+    // folds col's position within the tile into lim_valid)
     if (vec && lim_valid >= 4) {
         const typename Arith<U>::V4 v = *reinterpret_cast<const typename Arith<U>::V4 *>(p + col);
         out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
@@ -213,21 +221,71 @@ __device__ __forceinline__ void load_row4(const U *__restrict__ p, int64_t col, 
     }
 }
 
-template <typename U, bool NEXT>
-__global__ __launch_bounds__(256, 2) void minplus_kernel(U *__restrict__ D, int32_t *__restrict__ NX,
-                                                         int64_t n, int64_t ld, int K, int BS,
-                                                         int phase, int nt, int vec) {
-    __shared__ __attribute__((aligned(16))) U As[KC][LDP];   // As[k][i] = A[i][k]
-    __shared__ __attribute__((aligned(16))) U Bs[KC][LDP];   // Bs[k][j] = B[k][j]
+// Operands of one k of the current chunk: a[] = A[rows of the patch][k],
+// b[] = B[k][columns of the patch].
+template <typename U, int NT>
+__device__ __forceinline__ void lds_operands(const U (*As)[LDP], const U (*Bs)[LDP], int kk, int tx,
+                                             int ty, U a[8], U b[Geo<NT>::cpt]) {
+    using V4 = typename Arith<U>::V4;
+    const V4 a0 = *reinterpret_cast<const V4 *>(&As[kk][ty * 4]);
+    const V4 a1 = *reinterpret_cast<const V4 *>(&As[kk][64 + ty * 4]);
+    a[0] = a0.x; a[1] = a0.y; a[2] = a0.z; a[3] = a0.w;
+    a[4] = a1.x; a[5] = a1.y; a[6] = a1.z; a[7] = a1.w;
+#pragma unroll
+    for (int g = 0; g < Geo<NT>::cpt / 4; ++g) {
+        const V4 c0 = *reinterpret_cast<const V4 *>(&Bs[kk][g * Geo<NT>::txn * 4 + tx * 4]);
+        b[4 * g + 0] = c0.x; b[4 * g + 1] = c0.y; b[4 * g + 2] = c0.z; b[4 * g + 3] = c0.w;
+    }
+}
 
-    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+template <typename U> __device__ __forceinline__ int as_int(U v) { return __builtin_bit_cast(int, v); }
+template <typename U> __device__ __forceinline__ U from_int(int v) { return __builtin_bit_cast(U, v); }
+
+// Orders LDS traffic between lanes of one wave (the LDS executes a wave's
+// accesses in issue order; this keeps the compiler from reordering them).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Successor bookkeeping of the min-plus kernel (template argument ARGMIN):
+//   0  distances only: two adds and one v_min3 per pair of k's; 256 threads,
+//      8 x 8 patches.
+//   1  eager reference variant: every relaxation compares, selects the
+//      distance and records k (four VALU operations per relaxation).
+//   2  deferred (default): 512 threads, 8 x 4 patches.  The k loop keeps the
+//      distances-only form on a per-chunk minimum cm; at the end of each chunk
+//      the entries with cm < acc (a strict improvement -- rare after the
+//      first rounds) are appended, by wave ballot, to a per-wave queue in
+//      LDS, and each lane then searches one queued entry over the chunk's
+//      k's, still in LDS, for the first k with A[i][k] + B[k][j] == cm.  The
+//      winning k is kept in an LDS byte matrix.
+// Variants 1 and 2 select the same k: the first one, in increasing order,
+// that reaches the final minimum when that minimum beats the old value.
+template <typename U, int ARGMIN, int PHASE, bool VEC>
+__global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 2 ? 4 : 1) void minplus_kernel(
+        U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int K, int BS, int nt) {
+    constexpr int NT = (ARGMIN == 2) ? 512 : 256;
+    using G = Geo<NT>;
+    constexpr int CPT = G::cpt;
+    constexpr bool NEXT = ARGMIN != 0;
+    constexpr int QCAP = 128;                                      // queue entries per wave
+    __shared__ __attribute__((aligned(16))) U As[KC][LDP];        // As[k][i] = A[i][k]
+    __shared__ __attribute__((aligned(16))) U Bs[KC][LDP];        // Bs[k][j] = B[k][j]
+    __shared__ uint32_t kst[ARGMIN == 2 ? kTile * kTile / 4 : 1]; // improving k per entry (bytes)
+    __shared__ uint32_t qpos[ARGMIN == 2 ? G::waves * QCAP : 1];  // queued entry: i | j << 8
+    __shared__ U qval[ARGMIN == 2 ? G::waves * QCAP : 1];         // its chunk minimum
+    __shared__ int qmin[ARGMIN == 2 ? G::waves * 64 : 1];         // per-entry search result
+
+    const int t = threadIdx.x, tx = t % G::txn, ty = t / G::txn;
     const int64_t b0 = (int64_t)K * BS;
     const int bk = (int)imin64((int64_t)BS, n - b0);
     const int64_t b1 = b0 + bk;
 
     int mode;             // 0 remainder, 1 row band, 2 column band
     int64_t row0, col0;
-    if (phase == 3) {
+    if (PHASE == 3) {
         const int64_t tiles = (int64_t)nt * nt;
         // Workgroups are dealt to the eight XCDs round-robin; give each XCD a
         // contiguous run of tiles so that tiles sharing a row of A meet in
@@ -254,19 +312,18 @@ __global__ __launch_bounds__(256, 2) void minplus_kernel(U *__restrict__ D, int3
     // number of valid rows / columns of C (and of A's rows, B's columns)
     const int rows_valid = (mode == 1) ? bk : (int)imin64(kTile, n - row0);
     const int cols_valid = (mode == 2) ? bk : (int)imin64(kTile, n - col0);
-    const bool use_vec = vec != 0;
+    constexpr bool use_vec = VEC;
 
     // ---- load C
-    U acc[8][8];
-    int32_t idx[8][8];
+    U acc[8][CPT];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-        const int li = patch_off(ty, r);
+        const int li = G::row_off(ty, r);
         const bool rv = li < rows_valid;
         const U *rowp = D + (row0 + (rv ? li : 0)) * ld + col0;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int lj = h * 64 + tx * 4;
+        for (int g = 0; g < CPT / 4; ++g) {
+            const int lj = G::col_off(tx, 4 * g);
             U v[4];
             if (rv) {
                 load_row4(rowp, lj, cols_valid - lj, use_vec, v);
@@ -275,23 +332,37 @@ __global__ __launch_bounds__(256, 2) void minplus_kernel(U *__restrict__ D, int3
                 for (int e = 0; e < 4; ++e) v[e] = Arith<U>::inf();
             }
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                acc[r][h * 4 + e] = v[e];
-                idx[r][h * 4 + e] = -1;
-            }
+            for (int e = 0; e < 4; ++e) acc[r][4 * g + e] = v[e];
         }
     }
+    int32_t idx[8][CPT];    // improving k (-1: none), later the new successor
+    if (ARGMIN == 1) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) idx[r][c] = -1;
+    }
+    if (ARGMIN == 2) {
+#pragma unroll
+        for (int q = t; q < kTile * kTile / 4; q += NT) kst[q] = 0xFFFFFFFFu;
+        for (int q = t; q < G::waves * 64; q += NT) qmin[q] = 0xFF;
+    }
+    const int lane = t & 63;
+    const int wq = (t >> 6) * QCAP;     // this wave's queue
+    const int wq64 = (t >> 6) * 64;     // this wave's search results
 
     // ---- k loop: stage KC k's of A and B in LDS, then relax
-    const int a_il = t >> 1, a_kq = (t & 1) * 16;     // A staging: row, first k
-    const int b_kk = t >> 3, b_jq = (t & 7) * 16;     // B staging: k, first column
+    constexpr int APT = KC * kTile / NT;          // A entries staged per thread
+    constexpr int BPT = KC * kTile / NT;          // B entries staged per thread
+    const int a_il = t / (KC / APT), a_kq = (t % (KC / APT)) * APT;
+    const int b_kk = t / (kTile / BPT), b_jq = (t % (kTile / BPT)) * BPT;
     for (int kc = 0; kc < bk; kc += KC) {
         if (kc) __syncthreads();
         {   // A: As[kk][il] = D[row0 + il][b0 + kc + kk]
             const bool rv = a_il < rows_valid;
             const U *p = D + (row0 + (rv ? a_il : 0)) * ld + b0 + kc;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < APT / 4; ++q) {
                 const int kk = a_kq + q * 4;
                 U v[4];
                 if (rv) {
@@ -308,7 +379,7 @@ __global__ __launch_bounds__(256, 2) void minplus_kernel(U *__restrict__ D, int3
             const bool kv = kc + b_kk < bk;
             const U *p = D + (b0 + kc + (kv ? b_kk : 0)) * ld + col0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < BPT / 4; ++q) {
                 const int jl = b_jq + q * 4;
                 U v[4];
                 if (kv) {
@@ -324,23 +395,16 @@ __global__ __launch_bounds__(256, 2) void minplus_kernel(U *__restrict__ D, int3
         }
         __syncthreads();
 
-        if (NEXT) {
+        if constexpr (ARGMIN == 1) {
 #pragma unroll 2
             for (int kk = 0; kk < KC; ++kk) {
-                U a[8], b[8];
-                const typename Arith<U>::V4 a0 = *reinterpret_cast<const typename Arith<U>::V4 *>(&As[kk][ty * 4]);
-                const typename Arith<U>::V4 a1 = *reinterpret_cast<const typename Arith<U>::V4 *>(&As[kk][64 + ty * 4]);
-                const typename Arith<U>::V4 c0 = *reinterpret_cast<const typename Arith<U>::V4 *>(&Bs[kk][tx * 4]);
-                const typename Arith<U>::V4 c1 = *reinterpret_cast<const typename Arith<U>::V4 *>(&Bs[kk][64 + tx * 4]);
-                a[0] = a0.x; a[1] = a0.y; a[2] = a0.z; a[3] = a0.w;
-                a[4] = a1.x; a[5] = a1.y; a[6] = a1.z; a[7] = a1.w;
-                b[0] = c0.x; b[1] = c0.y; b[2] = c0.z; b[3] = c0.w;
-                b[4] = c1.x; b[5] = c1.y; b[6] = c1.z; b[7] = c1.w;
+                U a[8], b[CPT];
+                lds_operands<U, NT>(As, Bs, kk, tx, ty, a, b);
                 const int kg = kc + kk;
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
 #pragma unroll
-                    for (int c = 0; c < 8; ++c) {
+                    for (int c = 0; c < CPT; ++c) {
                         const U s = a[r] + b[c];
                         const bool lt = s < acc[r][c];
                         acc[r][c] = lt ? s : acc[r][c];
@@ -348,46 +412,152 @@ __global__ __launch_bounds__(256, 2) void minplus_kernel(U *__restrict__ D, int3
                     }
                 }
             }
-        } else {
+        } else if constexpr (ARGMIN == 0) {
 #pragma unroll 1
             for (int kk = 0; kk < KC; kk += 2) {
-                U a[8], b[8], a2[8], b2[8];
-                const typename Arith<U>::V4 a0 = *reinterpret_cast<const typename Arith<U>::V4 *>(&As[kk][ty * 4]);
-                const typename Arith<U>::V4 a1 = *reinterpret_cast<const typename Arith<U>::V4 *>(&As[kk][64 + ty * 4]);
-                const typename Arith<U>::V4 c0 = *reinterpret_cast<const typename Arith<U>::V4 *>(&Bs[kk][tx * 4]);
-                const typename Arith<U>::V4 c1 = *reinterpret_cast<const typename Arith<U>::V4 *>(&Bs[kk][64 + tx * 4]);
-                const typename Arith<U>::V4 e0 = *reinterpret_cast<const typename Arith<U>::V4 *>(&As[kk + 1][ty * 4]);
-                const typename Arith<U>::V4 e1 = *reinterpret_cast<const typename Arith<U>::V4 *>(&As[kk + 1][64 + ty * 4]);
-                const typename Arith<U>::V4 f0 = *reinterpret_cast<const typename Arith<U>::V4 *>(&Bs[kk + 1][tx * 4]);
-                const typename Arith<U>::V4 f1 = *reinterpret_cast<const typename Arith<U>::V4 *>(&Bs[kk + 1][64 + tx * 4]);
-                a[0] = a0.x; a[1] = a0.y; a[2] = a0.z; a[3] = a0.w;
-                a[4] = a1.x; a[5] = a1.y; a[6] = a1.z; a[7] = a1.w;
-                b[0] = c0.x; b[1] = c0.y; b[2] = c0.z; b[3] = c0.w;
-                b[4] = c1.x; b[5] = c1.y; b[6] = c1.z; b[7] = c1.w;
-                a2[0] = e0.x; a2[1] = e0.y; a2[2] = e0.z; a2[3] = e0.w;
-                a2[4] = e1.x; a2[5] = e1.y; a2[6] = e1.z; a2[7] = e1.w;
-                b2[0] = f0.x; b2[1] = f0.y; b2[2] = f0.z; b2[3] = f0.w;
-                b2[4] = f1.x; b2[5] = f1.y; b2[6] = f1.z; b2[7] = f1.w;
+                U a[8], b[CPT], a2[8], b2[CPT];
+                lds_operands<U, NT>(As, Bs, kk, tx, ty, a, b);
+                lds_operands<U, NT>(As, Bs, kk + 1, tx, ty, a2, b2);
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
 #pragma unroll
-                    for (int c = 0; c < 8; ++c) {
+                    for (int c = 0; c < CPT; ++c) {
                         acc[r][c] = Arith<U>::mn(acc[r][c], Arith<U>::mn(a[r] + b[c], a2[r] + b2[c]));
                     }
+                }
+            }
+        } else {
+            U cm[8][CPT];   // minimum over this chunk
+            {
+                U a[8], b[CPT], a2[8], b2[CPT];
+                lds_operands<U, NT>(As, Bs, 0, tx, ty, a, b);
+                lds_operands<U, NT>(As, Bs, 1, tx, ty, a2, b2);
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c) cm[r][c] = Arith<U>::mn(a[r] + b[c], a2[r] + b2[c]);
+            }
+#pragma unroll 1
+            for (int kk = 2; kk < KC; kk += 2) {
+                U a[8], b[CPT], a2[8], b2[CPT];
+                lds_operands<U, NT>(As, Bs, kk, tx, ty, a, b);
+                lds_operands<U, NT>(As, Bs, kk + 1, tx, ty, a2, b2);
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c) {
+                        cm[r][c] = Arith<U>::mn(cm[r][c], Arith<U>::mn(a[r] + b[c], a2[r] + b2[c]));
+                    }
+                }
+            }
+            // ---- strict improvements of this chunk (cm < acc): find the first k
+            // of each while the chunk is still in LDS.  Scanning k downwards and
+            // keeping every hit leaves the smallest one.
+            // Opaque copies of tx, ty: addresses derived from them are then
+            // computed here, not hoisted out of the chunk loop into registers.
+            int txo = tx, tyo = ty;
+            asm volatile("" : "+v"(txo), "+v"(tyo));
+            // Each pass queues whole patch slots, in order, while they fit in
+            // the QCAP-entry queue (a slot adds at most 64), folds them into
+            // acc, then searches the queued entries with all 64 lanes.  One pass
+            // suffices unless more than QCAP entries improved (the first rounds).
+            const uint32_t ebase = (uint32_t)(tyo * 4) | ((uint32_t)(txo * 4) << 8);
+            int s0 = 0;                                  // first slot not yet handled
+            while (s0 < 8 * CPT) {
+                int qcnt = 0, s1 = s0;
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c) {
+                        const int slot = r * CPT + c;
+                        if (slot == s1) {                // uniform
+                            const bool imp = cm[r][c] < acc[r][c];
+                            const uint64_t m = __builtin_amdgcn_ballot_w64(imp);
+                            const int cnt = __builtin_popcountll(m);
+                            if (qcnt + cnt <= QCAP) {
+                                if (imp) {
+                                    const int pos = qcnt + (int)__builtin_amdgcn_mbcnt_hi(
+                                                               (uint32_t)(m >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                                    qpos[wq + pos] = ebase + (uint32_t)(G::row_off(0, r) | (G::col_off(0, c) << 8));
+                                    qval[wq + pos] = cm[r][c];
+                                }
+                                qcnt += cnt;
+                                acc[r][c] = Arith<U>::mn(acc[r][c], cm[r][c]);
+                                s1 = slot + 1;
+                            }
+                        }
+                    }
+                }
+                s0 = s1;
+                // m entries per batch; each gets L = 64 / m lanes (a power of two,
+                // at most KC); lane o of an entry scans k = o*span .. o*span+span-1
+                // and the entry's answer is the smallest hit over its lanes.
+                for (int base = 0; base < qcnt; base += 64) {
+                    const int m = (qcnt - base < 64) ? qcnt - base : 64;
+                    wave_sync();
+                    const int cl2 = (m <= 1) ? 0 : 32 - __builtin_clz((uint32_t)(m - 1));   // ceil(log2 m)
+                    const int lg = (6 - cl2 < 5) ? 6 - cl2 : 5;                             // log2 L
+                    const int span = KC >> lg;
+                    const int e = lane >> lg, o = lane & ((1 << lg) - 1);
+                    int li = 0, lj = 0, kb = 0xFF;
+                    if (e < m) {
+                        const uint32_t ent = qpos[wq + base + e];
+                        li = (int)(ent & 0xFFu);
+                        lj = (int)(ent >> 8);
+                        const U tgt = qval[wq + base + e];
+                        const int k0 = o * span;
+                        int q = span - 1;
+                        for (; q >= 3; q -= 4) {
+                            const U x0 = As[k0 + q][li] + Bs[k0 + q][lj];
+                            const U x1 = As[k0 + q - 1][li] + Bs[k0 + q - 1][lj];
+                            const U x2 = As[k0 + q - 2][li] + Bs[k0 + q - 2][lj];
+                            const U x3 = As[k0 + q - 3][li] + Bs[k0 + q - 3][lj];
+                            kb = (x0 == tgt) ? k0 + q : kb;
+                            kb = (x1 == tgt) ? k0 + q - 1 : kb;
+                            kb = (x2 == tgt) ? k0 + q - 2 : kb;
+                            kb = (x3 == tgt) ? k0 + q - 3 : kb;
+                        }
+                        for (; q >= 0; --q) kb = (As[k0 + q][li] + Bs[k0 + q][lj] == tgt) ? k0 + q : kb;
+                    }
+                    if (lg == 0) {
+                        if (e < m) reinterpret_cast<uint8_t *>(kst)[li * kTile + lj] = (uint8_t)(kc + kb);
+                    } else {
+                        if (e < m && kb != 0xFF) atomicMin(&qmin[wq64 + e], kb);
+                        wave_sync();
+                        if (e < m && o == 0) {
+                            reinterpret_cast<uint8_t *>(kst)[li * kTile + lj] = (uint8_t)(kc + qmin[wq64 + e]);
+                            qmin[wq64 + e] = 0xFF;
+                        }
+                    }
+                    wave_sync();
                 }
             }
         }
     }
 
     // ---- successor gather (reads A's NX before anything is written: for the
-    // column band A is C itself)
+    // column band A is C itself).  Afterwards idx holds the new successor of
+    // an improved entry (>= 0: its A entry is finite) and -1 elsewhere.
     if (NEXT) {
+        if (ARGMIN == 2) {
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const uint32_t w = kst[(G::row_off(ty, r) * kTile + G::col_off(tx, 0)) >> 2];
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    const uint32_t kb = (w >> (8 * c)) & 0xFFu;
+                    idx[r][c] = kb == 0xFFu ? -1 : (int32_t)kb;
+                }
+            }
+        }
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-            const int li = patch_off(ty, r);
+            const int li = G::row_off(ty, r);
             const int32_t *nrow = NX + (row0 + (li < rows_valid ? li : 0)) * ld + b0;
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
+            for (int c = 0; c < CPT; ++c) {
                 if (idx[r][c] >= 0) idx[r][c] = nrow[idx[r][c]];
             }
         }
@@ -397,7 +567,7 @@ __global__ __launch_bounds__(256, 2) void minplus_kernel(U *__restrict__ D, int3
     // ---- store (rows / columns of the band itself are not part of phase 3)
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-        const int li = patch_off(ty, r);
+        const int li = G::row_off(ty, r);
         const int64_t gi = row0 + li;
         bool rs = li < rows_valid;
         if (mode != 1) rs = rs && !(gi >= b0 && gi < b1);
@@ -405,8 +575,8 @@ __global__ __launch_bounds__(256, 2) void minplus_kernel(U *__restrict__ D, int3
         U *drow = D + gi * ld + col0;
         int32_t *nrow = NEXT ? NX + gi * ld + col0 : nullptr;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int lj = h * 64 + tx * 4;
+        for (int g = 0; g < CPT / 4; ++g) {
+            const int lj = G::col_off(tx, 4 * g);
             bool cs[4];
             bool all = true;
 #pragma unroll
@@ -416,37 +586,35 @@ __global__ __launch_bounds__(256, 2) void minplus_kernel(U *__restrict__ D, int3
                 all = all && cs[e];
             }
             if (NEXT) {
-                // Only improved entries change.  After the gather idx holds the
-                // successor of an improved entry (>= 0: its A entry is finite)
-                // and -1 elsewhere.
+                // only improved entries change
                 bool ch[4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) ch[e] = cs[e] && idx[r][h * 4 + e] >= 0;
+                for (int e = 0; e < 4; ++e) ch[e] = cs[e] && idx[r][4 * g + e] >= 0;
                 if (use_vec && all) {
                     if (ch[0] || ch[1] || ch[2] || ch[3]) {
                         typename Arith<U>::V4 w;
-                        w.x = acc[r][h * 4 + 0]; w.y = acc[r][h * 4 + 1];
-                        w.z = acc[r][h * 4 + 2]; w.w = acc[r][h * 4 + 3];
+                        w.x = acc[r][4 * g + 0]; w.y = acc[r][4 * g + 1];
+                        w.z = acc[r][4 * g + 2]; w.w = acc[r][4 * g + 3];
                         *reinterpret_cast<typename Arith<U>::V4 *>(drow + lj) = w;
                     }
                 } else {
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
-                        if (ch[e]) drow[lj + e] = acc[r][h * 4 + e];
+                        if (ch[e]) drow[lj + e] = acc[r][4 * g + e];
                 }
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    if (ch[e]) nrow[lj + e] = idx[r][h * 4 + e];
+                    if (ch[e]) nrow[lj + e] = idx[r][4 * g + e];
             } else {
                 if (use_vec && all) {
                     typename Arith<U>::V4 w;
-                    w.x = acc[r][h * 4 + 0]; w.y = acc[r][h * 4 + 1];
-                    w.z = acc[r][h * 4 + 2]; w.w = acc[r][h * 4 + 3];
+                    w.x = acc[r][4 * g + 0]; w.y = acc[r][4 * g + 1];
+                    w.z = acc[r][4 * g + 2]; w.w = acc[r][4 * g + 3];
                     *reinterpret_cast<typename Arith<U>::V4 *>(drow + lj) = w;
                 } else {
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
-                        if (cs[e]) drow[lj + e] = acc[r][h * 4 + e];
+                        if (cs[e]) drow[lj + e] = acc[r][4 * g + e];
                 }
             }
         }
@@ -472,18 +640,23 @@ hipError_t phase1_t(const Plan &p, int K) {
     return hipGetLastError();
 }
 
-template <typename U, bool NEXT>
+template <typename U, int ARGMIN, bool VEC>
 hipError_t minplus_t(const Plan &p, int K, int phase) {
-    dim3 grid;
+    constexpr int NT = (ARGMIN == 2) ? 512 : 256;
     if (phase == 2) {
-        grid = dim3((unsigned)p.nt, 2);
+        hipLaunchKernelGGL((minplus_kernel<U, ARGMIN, 2, VEC>), dim3((unsigned)p.nt, 2), dim3(NT), 0, p.stream,
+                           (U *)p.dist, p.next, p.n, p.ld, K, p.bs, p.nt);
     } else {
         const int64_t tiles = (int64_t)p.nt * p.nt;
-        grid = dim3((unsigned)(8 * ((tiles + 7) / 8)));
+        hipLaunchKernelGGL((minplus_kernel<U, ARGMIN, 3, VEC>), dim3((unsigned)(8 * ((tiles + 7) / 8))), dim3(NT),
+                           0, p.stream, (U *)p.dist, p.next, p.n, p.ld, K, p.bs, p.nt);
     }
-    hipLaunchKernelGGL((minplus_kernel<U, NEXT>), grid, dim3(256), 0, p.stream, (U *)p.dist, p.next,
-                       p.n, p.ld, K, p.bs, phase, p.nt, p.vec ? 1 : 0);
     return hipGetLastError();
+}
+
+template <typename U, int ARGMIN>
+hipError_t minplus_v(const Plan &p, int K, int phase) {
+    return p.vec ? minplus_t<U, ARGMIN, true>(p, K, phase) : minplus_t<U, ARGMIN, false>(p, K, phase);
 }
 
 }  // namespace
@@ -497,14 +670,18 @@ hipError_t launch_phase1(const Plan &p, int K) {
     return p.next ? phase1_t<float, true>(p, K) : phase1_t<float, false>(p, K);
 }
 
+template <typename U>
+hipError_t minplus_dispatch(const Plan &p, int K, int phase) {
+    if (!p.next) return minplus_v<U, 0>(p, K, phase);
+    return p.eager_argmin ? minplus_v<U, 1>(p, K, phase) : minplus_v<U, 2>(p, K, phase);
+}
+
 hipError_t launch_phase2(const Plan &p, int K) {
-    if (p.dtype == DType::I32) return p.next ? minplus_t<uint32_t, true>(p, K, 2) : minplus_t<uint32_t, false>(p, K, 2);
-    return p.next ? minplus_t<float, true>(p, K, 2) : minplus_t<float, false>(p, K, 2);
+    return p.dtype == DType::I32 ? minplus_dispatch<uint32_t>(p, K, 2) : minplus_dispatch<float>(p, K, 2);
 }
 
 hipError_t launch_phase3(const Plan &p, int K) {
-    if (p.dtype == DType::I32) return p.next ? minplus_t<uint32_t, true>(p, K, 3) : minplus_t<uint32_t, false>(p, K, 3);
-    return p.next ? minplus_t<float, true>(p, K, 3) : minplus_t<float, false>(p, K, 3);
+    return p.dtype == DType::I32 ? minplus_dispatch<uint32_t>(p, K, 3) : minplus_dispatch<float>(p, K, 3);
 }
 
 }  // namespace fw

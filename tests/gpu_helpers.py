@@ -18,7 +18,7 @@ def log(msg):
     sys.stdout.flush()
 
 
-def gpu_solve(W, next_hop=True, block=0, schedule=0, ld=None, stream=None):
+def gpu_solve(W, next_hop=True, block=0, schedule=0, ld=None, stream=None, flags=0):
     """Copy W to the GPU (optionally into an n x ld buffer), solve, copy back."""
     import torch
     import paper_2403_18619_amd as fw
@@ -28,7 +28,7 @@ def gpu_solve(W, next_hop=True, block=0, schedule=0, ld=None, stream=None):
     D = torch.empty((n, max(ld, 1)), dtype=dt, device="cuda")[:, :n]
     D.copy_(torch.from_numpy(np.ascontiguousarray(W)))
     NX = torch.empty((n, max(ld, 1)), dtype=torch.int32, device="cuda")[:, :n] if next_hop else None
-    fw.solve_(D, NX, block=block, schedule=schedule, stream=stream)
+    fw.solve_(D, NX, block=block, schedule=schedule, stream=stream, flags=flags)
     fw.check(stream)
     torch.cuda.synchronize()
     return D.cpu().numpy(), (NX.cpu().numpy() if next_hop else None)

@@ -1,0 +1,80 @@
+"""GPU parity at the measured sizes, in the launch configuration bench.py
+times (default block size and schedule).
+
+  - n = 4096 with the headline recipe (edge prob 0.8, int32 U[1,10000]):
+    full oracle run, bit-exact, every successor walk;
+  - n = 8192 complete graph, float32 U[0,1): full float64 oracle run,
+    relative 1e-5, successor walks on sampled rows;
+  - n = 32768 headline graph: Dijkstra from sampled sources (rows 0, n-1 and
+    seeded random rows), bit-exact, walks and triangle inequality on them.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_helpers import INF, assert_close_f32, assert_walks, log
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve_device(W, flags=0):
+    import torch
+    import paper_2403_18619_amd as fw
+    Wd = torch.from_numpy(W).cuda()
+    D, NX = fw.solve(Wd, flags=flags)
+    fw.check()
+    del Wd
+    return D, NX
+
+
+def test_headline_recipe_n4096_full():
+    log("case headline recipe n=4096 full oracle")
+    W = synth.sparse80_i32(4096)
+    D, NX = oracle.fw_i32(W)
+    Dg, NXg = _solve_device(W)
+    Dg, NXg = Dg.cpu().numpy(), NXg.cpu().numpy()
+    np.testing.assert_array_equal(Dg, D)
+    assert_walks(W, Dg, NXg)
+
+
+def test_dense_f32_n8192_full():
+    log("case dense f32 n=8192 full float64 oracle")
+    import torch
+    import paper_2403_18619_amd as fw
+    W = synth.dense_f32(8192)
+    Dg, NXg = _solve_device(W)
+    D2, N2 = _solve_device(W, flags=fw.FLAG_EAGER_ARGMIN)
+    assert torch.equal(Dg.view(torch.int32), D2.view(torch.int32)) and torch.equal(NXg, N2)
+    del D2, N2
+    Dg, NXg = Dg.cpu().numpy(), NXg.cpu().numpy()
+    D64, _ = oracle.fw_f64(W, next_hop=False)
+    assert_close_f32(Dg, D64)
+    rows = np.unique(np.concatenate([[0, 8191], np.random.default_rng(2).integers(0, 8192, 62)]))
+    assert_walks(W, Dg, NXg, rows=rows)
+
+
+def test_headline_n32768_sampled_rows():
+    log("case headline n=32768 sampled rows")
+    n = 32768
+    W = synth.sparse80_i32(n)
+    D, NX = _solve_device(W)
+    rows = np.unique(np.concatenate([[0, n - 1], np.random.default_rng(3).integers(0, n, 14)]))
+    Dr = D[torch_index(rows)].cpu().numpy()
+    ref = oracle.sssp_i32(W, rows)
+    np.testing.assert_array_equal(Dr, ref)
+    # walks on the sampled rows need the full successor matrix on the host
+    Dh, NXh = D.cpu().numpy(), NX.cpu().numpy()
+    del D, NX
+    assert_walks(W, Dh, NXh, rows=rows)
+    # triangle inequality D[i][j] <= D[i][k] + D[k][j] for sampled i, k and all j
+    ks = np.random.default_rng(4).integers(0, n, 16)
+    Di = Dh[rows].astype(np.int64)
+    for k in ks:
+        assert (Di <= Di[:, k:k + 1] + Dh[k].astype(np.int64)[None, :]).all()
+    assert (Dh[rows] <= np.where(W[rows] >= INF, INF, W[rows])).all()        # D <= W
+
+
+def torch_index(rows):
+    import torch
+    return torch.from_numpy(np.asarray(rows, np.int64)).cuda()
