@@ -457,22 +457,24 @@ __global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 2 ? 4 : 1) void 
             // computed here, not hoisted out of the chunk loop into registers.
             int txo = tx, tyo = ty;
             asm volatile("" : "+v"(txo), "+v"(tyo));
-            // Each pass queues whole patch slots, in order, while they fit in
-            // the QCAP-entry queue (a slot adds at most 64), folds them into
-            // acc, then searches the queued entries with all 64 lanes.  One pass
-            // suffices unless more than QCAP entries improved (the first rounds).
+            // Each pass queues the improved entries of every slot that still fits
+            // in the QCAP-entry queue (a slot adds at most 64), folds those slots
+            // into acc -- which makes cm < acc false for them, so a later pass
+            // skips them -- and then searches the queue with all 64 lanes.  One
+            // pass suffices unless more than QCAP entries improved (the first
+            // rounds).  A slot with no improvement costs one compare and branch.
             const uint32_t ebase = (uint32_t)(tyo * 4) | ((uint32_t)(txo * 4) << 8);
-            int s0 = 0;                                  // first slot not yet handled
-            while (s0 < 8 * CPT) {
-                int qcnt = 0, s1 = s0;
+            bool again;
+            do {
+                int qcnt = 0;
+                again = false;
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
 #pragma unroll
                     for (int c = 0; c < CPT; ++c) {
-                        const int slot = r * CPT + c;
-                        if (slot == s1) {                // uniform
-                            const bool imp = cm[r][c] < acc[r][c];
-                            const uint64_t m = __builtin_amdgcn_ballot_w64(imp);
+                        const bool imp = cm[r][c] < acc[r][c];
+                        const uint64_t m = __builtin_amdgcn_ballot_w64(imp);
+                        if (m) {                                     // uniform
                             const int cnt = __builtin_popcountll(m);
                             if (qcnt + cnt <= QCAP) {
                                 if (imp) {
@@ -484,12 +486,12 @@ __global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 2 ? 4 : 1) void 
                                 }
                                 qcnt += cnt;
                                 acc[r][c] = Arith<U>::mn(acc[r][c], cm[r][c]);
-                                s1 = slot + 1;
+                            } else {
+                                again = true;
                             }
                         }
                     }
                 }
-                s0 = s1;
                 // m entries per batch; each gets L = 64 / m lanes (a power of two,
                 // at most KC); lane o of an entry scans k = o*span .. o*span+span-1
                 // and the entry's answer is the smallest hit over its lanes.
@@ -532,7 +534,7 @@ __global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 2 ? 4 : 1) void 
                     }
                     wave_sync();
                 }
-            }
+            } while (again);
         }
     }
 
