@@ -538,6 +538,11 @@ __global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 2 ? 4 : 1) void 
         }
     }
 
+    // The epilogue recomputes its addresses from opaque copies of tx and ty
+    // rather than keeping the prologue's live across the k loop.
+    int txe = tx, tye = ty;
+    asm volatile("" : "+v"(txe), "+v"(tye));
+
     // ---- successor gather (reads A's NX before anything is written: for the
     // column band A is C itself).  Afterwards idx holds the new successor of
     // an improved entry (>= 0: its A entry is finite) and -1 elsewhere.
@@ -546,7 +551,7 @@ __global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 2 ? 4 : 1) void 
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
-                const uint32_t w = kst[(G::row_off(ty, r) * kTile + G::col_off(tx, 0)) >> 2];
+                const uint32_t w = kst[(G::row_off(tye, r) * kTile + G::col_off(txe, 0)) >> 2];
 #pragma unroll
                 for (int c = 0; c < CPT; ++c) {
                     const uint32_t kb = (w >> (8 * c)) & 0xFFu;
@@ -556,7 +561,7 @@ __global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 2 ? 4 : 1) void 
         }
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-            const int li = G::row_off(ty, r);
+            const int li = G::row_off(tye, r);
             const int32_t *nrow = NX + (row0 + (li < rows_valid ? li : 0)) * ld + b0;
 #pragma unroll
             for (int c = 0; c < CPT; ++c) {
@@ -569,7 +574,7 @@ __global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 2 ? 4 : 1) void 
     // ---- store (rows / columns of the band itself are not part of phase 3)
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-        const int li = G::row_off(ty, r);
+        const int li = G::row_off(tye, r);
         const int64_t gi = row0 + li;
         bool rs = li < rows_valid;
         if (mode != 1) rs = rs && !(gi >= b0 && gi < b1);
@@ -578,7 +583,7 @@ __global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 2 ? 4 : 1) void 
         int32_t *nrow = NEXT ? NX + gi * ld + col0 : nullptr;
 #pragma unroll
         for (int g = 0; g < CPT / 4; ++g) {
-            const int lj = G::col_off(tx, 4 * g);
+            const int lj = G::col_off(txe, 4 * g);
             bool cs[4];
             bool all = true;
 #pragma unroll
