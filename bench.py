@@ -47,7 +47,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload_key: str, per_launch_bytes_alg: float):
+def load_traffic(workload_key: str):
     """HBM traffic of the phase-3 kernel from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "phase3_traffic.json")
@@ -167,15 +167,12 @@ def main():
     relax_per_launch = relax_per_solve / (k_launches / args.steps)
     avg_s = k_ms / k_launches / 1e3
     achieved = OPS_PER_RELAX * relax_per_launch / avg_s
-    esz = 4
-    alg_bytes = None
-    traffic = load_traffic(f"{args.dtype}_n{n}_bs{bs}_{'next' if NX is not None else 'dist'}", alg_bytes)
+    traffic = load_traffic(f"{args.dtype}_n{n}_bs{bs}_{'next' if NX is not None else 'dist'}")
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
                 "unit": "Top/s", "frac": achieved / VALU_PEAK_LANE_OPS, "traffic": traffic,
                 "kernel": kind, "avg_launch_ms": avg_s * 1e3, "launches_per_step": k_launches / args.steps,
                 "ops_per_relaxation": OPS_PER_RELAX}
     phase_ms = {k: (v[0] / args.steps) for k, v in ph.items() if v[1]}
-    del esz
 
     cpu = None
     if not args.no_cpu_baseline:
