@@ -61,9 +61,11 @@ typedef enum fw_status {
 #define FW_INF_I32 1073741824   /* 2^30: int32 "no edge" and unreachable */
 
 /* Schedules (fw_options.schedule). */
-#define FW_SCHED_AUTO 0         /* library's choice                          */
+#define FW_SCHED_AUTO 0         /* library's choice: persistent, except three
+                                   launches for successor solves at n >= 16384 */
 #define FW_SCHED_THREE_LAUNCH 1 /* per round: phase 1, phase 2, phase 3      */
-#define FW_SCHED_PERSISTENT 2   /* one launch, per-tile dependency flags     */
+#define FW_SCHED_PERSISTENT 2   /* one launch, per-tile dependency flags;
+                                   block size 128 only                       */
 
 typedef struct fw_options {
     int32_t block;     /* block size BS (k-depth of one round): 0 = auto, or 32, 64, 128 */
@@ -81,6 +83,10 @@ typedef struct fw_options {
  * compares and records k at every relaxation (about 2.5x slower).  It selects
  * the same successors as the default, bit for bit; tests use it as a check. */
 #define FW_FLAG_EAGER_ARGMIN 2
+/* fw_options.flags, tests only: the persistent schedule's dependency waits
+ * get a zero time bound, so a solve ends early with FW_ERR_TIMEOUT (reported
+ * by fw_check) and unspecified output. */
+#define FW_FLAG_TEST_TIMEOUT 4
 
 /* Solve in place (Section 2.3, blocked form with block size BS).
  *   dist : n x n (storage n x ld) int32 / float32 weights in, distances out.

@@ -25,6 +25,7 @@ FW_INF_I32 = 1 << 30
 SCHED_AUTO, SCHED_THREE_LAUNCH, SCHED_PERSISTENT = 0, 1, 2
 FLAG_TIME_PHASES = 1
 FLAG_EAGER_ARGMIN = 2
+FLAG_TEST_TIMEOUT = 4
 PHASE_KINDS = ("init", "phase1", "phase2", "phase3", "persistent")
 
 
@@ -40,6 +41,9 @@ class FwError(RuntimeError):
 
 
 def _load():
+    # torch ships its own HIP runtime (same soname as the system one); loading
+    # it first makes the library bind to it, so the process has one runtime.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run `python paper_2403_18619_amd/build.py` "
                           "(hipcc, gfx950); there is no CPU fallback")

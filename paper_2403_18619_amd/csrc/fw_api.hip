@@ -59,7 +59,7 @@ fw_status check_args(const void *dist, int64_t n, int64_t ld, const fw_options *
             return fail(FW_ERR_INVALID_ARG, "block = %d (allowed: 0, 32, 64, 128)", opt->block);
         if (opt->schedule < FW_SCHED_AUTO || opt->schedule > FW_SCHED_PERSISTENT)
             return fail(FW_ERR_INVALID_ARG, "schedule = %d", opt->schedule);
-        if (opt->flags & ~(FW_FLAG_TIME_PHASES | FW_FLAG_EAGER_ARGMIN)) return fail(FW_ERR_INVALID_ARG, "flags = %d (unknown bits)", opt->flags);
+        if (opt->flags & ~(FW_FLAG_TIME_PHASES | FW_FLAG_EAGER_ARGMIN | FW_FLAG_TEST_TIMEOUT)) return fail(FW_ERR_INVALID_ARG, "flags = %d (unknown bits)", opt->flags);
     }
     return FW_OK;
 }
@@ -101,6 +101,36 @@ hipError_t timed(bool on, int kind, hipStream_t st, F fn) {
     return hipSuccess;
 }
 
+// Persistent schedule: flag workspace of the right size (grown on demand;
+// the old one is freed, which waits for the device) and the wait bound.
+fw_status persistent_plan(fw::Plan &p, bool test_timeout) {
+    const int64_t need = fw::persistent_workspace_ints(p.rounds, p.nt);
+    hipError_t e;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (p.work->persist_ints < need) {
+            if (p.work->persist) {
+                e = hipFree(p.work->persist);
+                if (e != hipSuccess) return hip_fail(e, "hipFree(persistent workspace)");
+                p.work->persist = nullptr;
+                p.work->persist_ints = 0;
+            }
+            e = hipMalloc(&p.work->persist, need * sizeof(int));
+            if (e != hipSuccess) return hip_fail(e, "hipMalloc(persistent workspace)");
+            p.work->persist_ints = need;
+        }
+    }
+    int dev = 0, khz = 0;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess) return hip_fail(e, "wall clock rate");
+    if (khz <= 0) khz = 100000;
+    // a wait never legitimately lasts longer than a few rounds; 20 s is far
+    // beyond that and still ends a stuck solve
+    p.timeout_ticks = test_timeout ? 0 : (uint64_t)khz * 1000ull * 20ull;
+    return FW_OK;
+}
+
 int auto_block(int64_t n) {
     if (n <= 32) return 32;
     if (n <= 64) return 64;
@@ -114,8 +144,14 @@ fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
     if (s != FW_OK || n == 0) return s;
     fw_options o = {0, FW_SCHED_AUTO, 0, 0};
     if (opt) o = *opt;
-    if (o.schedule == FW_SCHED_PERSISTENT)
-        return fail(FW_ERR_UNSUPPORTED, "persistent schedule is not available in this build");
+    // Automatic schedule (measured on MI355X): one persistent launch hides
+    // phase 1 and 2 behind the previous round and removes launch gaps; only
+    // large solves with successors run slightly faster as three launches.
+    bool persistent = o.schedule == FW_SCHED_PERSISTENT;
+    if (o.schedule == FW_SCHED_AUTO)
+        persistent = (o.block == 0 || o.block == fw::kTile) && n > fw::kTile && !(next && n >= 16384);
+    if (persistent && o.block != 0 && o.block != fw::kTile)
+        return fail(FW_ERR_UNSUPPORTED, "the persistent schedule runs block size %d only", fw::kTile);
 
     fw::Plan p;
     p.dtype = dt;
@@ -123,19 +159,29 @@ fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
     p.next = next;
     p.n = n;
     p.ld = ld;
-    p.bs = o.block ? o.block : auto_block(n);
+    p.bs = persistent ? fw::kTile : (o.block ? o.block : auto_block(n));
     p.rounds = (int)((n + p.bs - 1) / p.bs);
     p.nt = (int)((n + fw::kTile - 1) / fw::kTile);
     p.vec = (ld % 4 == 0) && ((uintptr_t)dist % 16 == 0);
     p.validate = o.validate != 0;
     p.eager_argmin = (o.flags & FW_FLAG_EAGER_ARGMIN) != 0;
+    p.timeout_ticks = 0;
     p.stream = (hipStream_t)stream;
     s = get_work(&p.work);
     if (s != FW_OK) return s;
 
     const bool tm = (o.flags & FW_FLAG_TIME_PHASES) != 0;
+    if (persistent) {
+        s = persistent_plan(p, (o.flags & FW_FLAG_TEST_TIMEOUT) != 0);
+        if (s != FW_OK) return s;
+    }
     hipError_t e = timed(tm, 0, p.stream, [&] { return fw::launch_init(p); });
     if (e != hipSuccess) return hip_fail(e, "init launch");
+    if (persistent) {
+        e = timed(tm, 4, p.stream, [&] { return fw::launch_persistent(p); });
+        if (e != hipSuccess) return hip_fail(e, "persistent launch");
+        return FW_OK;
+    }
     for (int K = 0; K < p.rounds; ++K) {
         e = timed(tm, 1, p.stream, [&] { return fw::launch_phase1(p, K); });
         if (e != hipSuccess) return hip_fail(e, "phase 1 launch");

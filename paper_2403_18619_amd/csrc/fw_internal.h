@@ -14,6 +14,8 @@ enum class DType { I32, F32 };
 // Per-device scratch owned by the library (a few words).
 struct DeviceWork {
     int *err = nullptr;        // device error word (0 = none)
+    int *persist = nullptr;    // persistent-schedule flags and counters
+    int64_t persist_ints = 0;  // their capacity
 };
 
 struct Plan {
@@ -27,6 +29,7 @@ struct Plan {
     bool vec;                  // 16-byte global accesses are legal
     bool validate;
     bool eager_argmin;         // successor variant: per-relaxation tracking
+    uint64_t timeout_ticks;    // persistent schedule: wait bound (100 MHz ticks)
     hipStream_t stream;
     DeviceWork *work;
 };
@@ -36,5 +39,7 @@ hipError_t launch_init(const Plan &p);
 hipError_t launch_phase1(const Plan &p, int K);
 hipError_t launch_phase2(const Plan &p, int K);
 hipError_t launch_phase3(const Plan &p, int K);
+hipError_t launch_persistent(const Plan &p);
+int64_t persistent_workspace_ints(int rounds, int nt);
 
 }  // namespace fw

@@ -87,89 +87,118 @@ __global__ __launch_bounds__(256) void init_kernel(U *__restrict__ D, int32_t *_
 
 // --------------------------------------------------------------- phase 1
 // Closure of the diagonal block in place (the paper's phase 1), one
-// workgroup.  Each thread keeps an M x M patch of the block in registers;
-// at step k only row k and column k are read, and they do not change during
-// step k (D[k][k] = 0, strict test), so the owners publish them into a
-// double-buffered LDS row / column and one barrier per step suffices.
-template <typename U, bool NEXT, int BS>
-__global__ __launch_bounds__(256) void phase1_kernel(U *__restrict__ D, int32_t *__restrict__ NX,
-                                                     int64_t n, int64_t ld, int K) {
-    constexpr int M = BS / 16;
-    __shared__ U rowb[2][BS];
-    __shared__ U colb[2][BS];
-    __shared__ int32_t nxb[2][BS];
-    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+// workgroup of NT threads.  Thread (tx, ty) of a TX x 16 grid keeps an
+// MR x MC patch of the block's distances in registers (rows ty*MR + r,
+// columns tx*MC + c).  At step k only row k and column k are read, and
+// neither they nor successor column k change during step k (D[k][k] = 0,
+// strict test), so the owners publish row / column k+1 into a double-buffered
+// LDS row / column and one barrier per step suffices.  The k loop is unrolled
+// by MR so that every register index is static.  Successors live in the
+// patch too (NXLDS = false: fastest, as a workgroup of its own) or in an LDS
+// copy of the block (NXLDS = true: fewer registers, inside the persistent
+// kernel); both give the same bits.
+template <typename U, int BS, bool NXLDS> struct Phase1Smem {
+    U rowb[2][BS];
+    U colb[2][BS];
+    int32_t nxb[NXLDS ? 1 : 2][BS];              // published successor column
+    int32_t nx[NXLDS ? BS : 1][BS + 1];          // odd pitch: column reads hit distinct banks
+};
+
+template <typename U, bool NEXT, int BS, int NT, bool NXLDS>
+__device__ __forceinline__ void phase1_block(U *__restrict__ D, int32_t *__restrict__ NX, int64_t n,
+                                             int64_t ld, int K, Phase1Smem<U, BS, NXLDS> &sm) {
+    constexpr int TX = NT / 16;
+    constexpr int MR = BS / 16, MC = BS / TX;
+    constexpr bool NXR = NEXT && !NXLDS;         // successors in registers
+    constexpr bool NXL = NEXT && NXLDS;          // successors in LDS
+    // an opaque thread index: per-thread addresses are derived here, on every
+    // call, instead of being hoisted into registers that live across callers
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    const int tx = t % TX, ty = t / TX;
     const int64_t b0 = (int64_t)K * BS;
     const int bk = (int)imin64((int64_t)BS, n - b0);
 
-    U d[M][M];
-    int32_t nx[M][M];
+    U d[MR][MC];
+    int32_t nx[NXR ? MR : 1][NXR ? MC : 1];
 #pragma unroll
-    for (int r = 0; r < M; ++r) {
+    for (int r = 0; r < MR; ++r) {
 #pragma unroll
-        for (int c = 0; c < M; ++c) {
-            const int li = ty * M + r, lj = tx * M + c;
-            if (li < bk && lj < bk) {
-                const int64_t o = (b0 + li) * ld + b0 + lj;
-                d[r][c] = D[o];
-                nx[r][c] = NEXT ? NX[o] : 0;
-            } else {
-                d[r][c] = (li == lj) ? U(0) : Arith<U>::inf();
-                nx[r][c] = -1;
-            }
+        for (int c = 0; c < MC; ++c) {
+            const int li = ty * MR + r, lj = tx * MC + c;
+            const bool in = li < bk && lj < bk;
+            if (in) d[r][c] = D[(b0 + li) * ld + b0 + lj];
+            else d[r][c] = (li == lj) ? U(0) : Arith<U>::inf();
+            if (NXR) nx[NXR ? r : 0][NXR ? c : 0] = in ? NX[(b0 + li) * ld + b0 + lj] : -1;
+        }
+    }
+    if (NXL) {
+        for (int q = t; q < bk * bk; q += NT) {
+            const int li = q / bk, lj = q % bk;
+            sm.nx[NXL ? li : 0][lj] = NX[(b0 + li) * ld + b0 + lj];
         }
     }
     if (ty == 0) {
 #pragma unroll
-        for (int c = 0; c < M; ++c) rowb[0][tx * M + c] = d[0][c];
+        for (int c = 0; c < MC; ++c) sm.rowb[0][tx * MC + c] = d[0][c];
     }
     if (tx == 0) {
 #pragma unroll
-        for (int r = 0; r < M; ++r) {
-            colb[0][ty * M + r] = d[r][0];
-            if (NEXT) nxb[0][ty * M + r] = nx[r][0];
+        for (int r = 0; r < MR; ++r) {
+            sm.colb[0][ty * MR + r] = d[r][0];
+            if (NXR) sm.nxb[0][ty * MR + r] = nx[NXR ? r : 0][0];
         }
     }
     __syncthreads();
 
-    for (int kb = 0; kb * M < bk; ++kb) {
+    for (int kb = 0; kb * MR < bk; ++kb) {
+        // opaque copies: LDS addresses are recomputed here rather than kept
+        // for every unrolled step
+        int txo = tx, tyo = ty;
+        asm volatile("" : "+v"(txo), "+v"(tyo));
 #pragma unroll
-        for (int r0 = 0; r0 < M; ++r0) {
-            const int k = kb * M + r0;
+        for (int u = 0; u < MR; ++u) {
+            const int k = kb * MR + u;
             if (k < bk) {                       // uniform across the workgroup
                 const int cur = k & 1;
-                U a[M], b[M];
-                int32_t na[M];
+                U a[MR], b[MC];
+                int32_t na[MR];
 #pragma unroll
-                for (int r = 0; r < M; ++r) {
-                    a[r] = colb[cur][ty * M + r];
-                    if (NEXT) na[r] = nxb[cur][ty * M + r];
+                for (int r = 0; r < MR; ++r) {
+                    a[r] = sm.colb[cur][tyo * MR + r];
+                    if (NXR) na[r] = sm.nxb[NXR ? cur : 0][tyo * MR + r];
+                    if (NXL) na[r] = sm.nx[NXL ? tyo * MR + r : 0][k];
                 }
 #pragma unroll
-                for (int c = 0; c < M; ++c) b[c] = rowb[cur][tx * M + c];
+                for (int c = 0; c < MC; ++c) b[c] = sm.rowb[cur][txo * MC + c];
 #pragma unroll
-                for (int r = 0; r < M; ++r) {
+                for (int r = 0; r < MR; ++r) {
 #pragma unroll
-                    for (int c = 0; c < M; ++c) {
+                    for (int c = 0; c < MC; ++c) {
                         const U s = a[r] + b[c];
                         const bool lt = s < d[r][c];
                         d[r][c] = lt ? s : d[r][c];
-                        if (NEXT) nx[r][c] = lt ? na[r] : nx[r][c];
+                        if (NXR) nx[NXR ? r : 0][NXR ? c : 0] = lt ? na[r] : nx[NXR ? r : 0][NXR ? c : 0];
+                        if (NXL && lt) sm.nx[NXL ? tyo * MR + r : 0][txo * MC + c] = na[r];
                     }
                 }
-                // publish row / column k+1 for the next step
-                const int r1 = (r0 + 1 == M) ? 0 : r0 + 1;
-                const int kb1 = (r0 + 1 == M) ? kb + 1 : kb;
-                if (k + 1 < bk) {
-                    if (ty == kb1) {
+                // publish row / column k+1 for the next step (owners and
+                // patch positions are static after unrolling)
+                const int k1 = k + 1;
+                const int rown = (u + 1 == MR) ? kb + 1 : kb;          // owner ty of row k1
+                const int r1 = (u + 1) % MR;
+                const int coln = (kb * MR + u + 1) / MC;               // owner tx of column k1
+                const int c1 = (u + 1) % MC;
+                if (k1 < bk) {
+                    if (tyo == rown) {
 #pragma unroll
-                        for (int c = 0; c < M; ++c) rowb[cur ^ 1][tx * M + c] = d[r1][c];
+                        for (int c = 0; c < MC; ++c) sm.rowb[cur ^ 1][txo * MC + c] = d[r1][c];
                     }
-                    if (tx == kb1) {
+                    if (txo == coln) {
 #pragma unroll
-                        for (int r = 0; r < M; ++r) {
-                            colb[cur ^ 1][ty * M + r] = d[r][r1];
-                            if (NEXT) nxb[cur ^ 1][ty * M + r] = nx[r][r1];
+                        for (int r = 0; r < MR; ++r) {
+                            sm.colb[cur ^ 1][tyo * MR + r] = d[r][c1];
+                            if (NXR) sm.nxb[NXR ? cur ^ 1 : 0][tyo * MR + r] = nx[NXR ? r : 0][NXR ? c1 : 0];
                         }
                     }
                 }
@@ -179,17 +208,29 @@ __global__ __launch_bounds__(256) void phase1_kernel(U *__restrict__ D, int32_t 
     }
 
 #pragma unroll
-    for (int r = 0; r < M; ++r) {
+    for (int r = 0; r < MR; ++r) {
 #pragma unroll
-        for (int c = 0; c < M; ++c) {
-            const int li = ty * M + r, lj = tx * M + c;
+        for (int c = 0; c < MC; ++c) {
+            const int li = ty * MR + r, lj = tx * MC + c;
             if (li < bk && lj < bk) {
-                const int64_t o = (b0 + li) * ld + b0 + lj;
-                D[o] = d[r][c];
-                if (NEXT) NX[o] = nx[r][c];
+                D[(b0 + li) * ld + b0 + lj] = d[r][c];
+                if (NXR) NX[(b0 + li) * ld + b0 + lj] = nx[NXR ? r : 0][NXR ? c : 0];
             }
         }
     }
+    if (NXL) {
+        for (int q = t; q < bk * bk; q += NT) {
+            const int li = q / bk, lj = q % bk;
+            NX[(b0 + li) * ld + b0 + lj] = sm.nx[NXL ? li : 0][lj];
+        }
+    }
+}
+
+template <typename U, bool NEXT, int BS>
+__global__ __launch_bounds__(256) void phase1_kernel(U *__restrict__ D, int32_t *__restrict__ NX,
+                                                     int64_t n, int64_t ld, int K) {
+    __shared__ Phase1Smem<U, BS, false> sm;
+    phase1_block<U, NEXT, BS, 256, false>(D, NX, n, ld, K, sm);
 }
 
 // ---------------------------------------------------- phases 2 and 3
@@ -263,52 +304,62 @@ __device__ __forceinline__ void wave_sync() {
 //      winning k is kept in an LDS byte matrix.
 // Variants 1 and 2 select the same k: the first one, in increasing order,
 // that reaches the final minimum when that minimum beats the old value.
-template <typename U, int ARGMIN, int PHASE, bool VEC>
-__global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 2 ? 4 : 1) void minplus_kernel(
-        U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int K, int BS, int nt) {
-    constexpr int NT = (ARGMIN == 2) ? 512 : 256;
+template <typename U, int ARGMIN> struct MinplusSmem {
+    static constexpr int NT = (ARGMIN == 2) ? 512 : 256;
+    static constexpr int QCAP = 128;                           // queue entries per wave
+    static constexpr int Q = (ARGMIN == 2) ? NT / 64 * QCAP : 1;
+    U As[KC][LDP];                                            // As[k][i] = A[i][k]
+    U Bs[KC][LDP];                                            // Bs[k][j] = B[k][j]
+    uint32_t kst[ARGMIN == 2 ? kTile * kTile / 4 : 1];       // improving k per entry (bytes)
+    uint32_t qpos[Q];                                         // queued entry: i | j << 8
+    U qval[Q];                                                // its chunk minimum
+    int qmin[ARGMIN == 2 ? NT : 1];                           // per-entry search result
+};
+
+// Where the tile of a min-plus launch lies.  mode 0: remainder (phase 3),
+// 1: row band, 2: column band (phase 2).  Returns false when every row or
+// every column of the tile belongs to the band (nothing to update there).
+__device__ __forceinline__ bool band_tile(int mode, int64_t idx, int64_t n, int64_t b0, int64_t b1,
+                                          int nt, int64_t &row0, int64_t &col0) {
+    if (mode == 0) {
+        row0 = (idx / nt) * kTile;
+        col0 = (idx % nt) * kTile;
+    } else if (mode == 1) {
+        row0 = b0;
+        col0 = idx * kTile;
+    } else {
+        row0 = idx * kTile;
+        col0 = b0;
+    }
+    if (mode != 1 && row0 >= b0 && imin64(row0 + kTile, n) <= b1) return false;
+    if (mode != 2 && col0 >= b0 && imin64(col0 + kTile, n) <= b1) return false;
+    return true;
+}
+
+// One 128 x 128 tile of C <- min(C, A (x) B) over the round's band.
+template <typename U, int ARGMIN, bool VEC>
+__device__ __forceinline__ void minplus_tile(U *__restrict__ D, int32_t *__restrict__ NX, int64_t n,
+                                             int64_t ld, int K, int BS, int mode, int64_t row0,
+                                             int64_t col0, MinplusSmem<U, ARGMIN> &sm) {
+    constexpr int NT = MinplusSmem<U, ARGMIN>::NT;
     using G = Geo<NT>;
     constexpr int CPT = G::cpt;
     constexpr bool NEXT = ARGMIN != 0;
-    constexpr int QCAP = 128;                                      // queue entries per wave
-    __shared__ __attribute__((aligned(16))) U As[KC][LDP];        // As[k][i] = A[i][k]
-    __shared__ __attribute__((aligned(16))) U Bs[KC][LDP];        // Bs[k][j] = B[k][j]
-    __shared__ uint32_t kst[ARGMIN == 2 ? kTile * kTile / 4 : 1]; // improving k per entry (bytes)
-    __shared__ uint32_t qpos[ARGMIN == 2 ? G::waves * QCAP : 1];  // queued entry: i | j << 8
-    __shared__ U qval[ARGMIN == 2 ? G::waves * QCAP : 1];         // its chunk minimum
-    __shared__ int qmin[ARGMIN == 2 ? G::waves * 64 : 1];         // per-entry search result
+    constexpr int QCAP = MinplusSmem<U, ARGMIN>::QCAP;
+    auto &As = sm.As;
+    auto &Bs = sm.Bs;
+    auto &kst = sm.kst;
+    auto &qpos = sm.qpos;
+    auto &qval = sm.qval;
+    auto &qmin = sm.qmin;
 
-    const int t = threadIdx.x, tx = t % G::txn, ty = t / G::txn;
+    // an opaque thread index (see phase1_block)
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    const int tx = t % G::txn, ty = t / G::txn;
     const int64_t b0 = (int64_t)K * BS;
     const int bk = (int)imin64((int64_t)BS, n - b0);
     const int64_t b1 = b0 + bk;
-
-    int mode;             // 0 remainder, 1 row band, 2 column band
-    int64_t row0, col0;
-    if (PHASE == 3) {
-        const int64_t tiles = (int64_t)nt * nt;
-        // Workgroups are dealt to the eight XCDs round-robin; give each XCD a
-        // contiguous run of tiles so that tiles sharing a row of A meet in
-        // the same L2.
-        const int64_t per = (tiles + 7) / 8;
-        const int64_t tid = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-        if (tid >= tiles) return;
-        row0 = (tid / nt) * kTile;
-        col0 = (tid % nt) * kTile;
-        if (row0 >= b0 && imin64(row0 + kTile, n) <= b1) return;   // all rows in the band
-        if (col0 >= b0 && imin64(col0 + kTile, n) <= b1) return;   // all columns in the band
-        mode = 0;
-    } else if (blockIdx.y == 0) {
-        mode = 1;
-        row0 = b0;
-        col0 = (int64_t)blockIdx.x * kTile;
-        if (col0 >= b0 && imin64(col0 + kTile, n) <= b1) return;
-    } else {
-        mode = 2;
-        row0 = (int64_t)blockIdx.x * kTile;
-        col0 = b0;
-        if (row0 >= b0 && imin64(row0 + kTile, n) <= b1) return;
-    }
     // number of valid rows / columns of C (and of A's rows, B's columns)
     const int rows_valid = (mode == 1) ? bk : (int)imin64(kTile, n - row0);
     const int cols_valid = (mode == 2) ? bk : (int)imin64(kTile, n - col0);
@@ -628,6 +679,274 @@ __global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 2 ? 4 : 1) void 
     }
 }
 
+template <typename U, int ARGMIN, int PHASE, bool VEC>
+__global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 2 ? 4 : 1) void minplus_kernel(
+        U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int K, int BS, int nt) {
+    __shared__ MinplusSmem<U, ARGMIN> sm;
+    const int64_t b0 = (int64_t)K * BS;
+    const int64_t b1 = b0 + imin64((int64_t)BS, n - b0);
+    int mode;
+    int64_t idx;
+    if (PHASE == 3) {
+        // Workgroups are dealt to the eight XCDs round-robin; give each XCD a
+        // contiguous run of tiles so that tiles sharing a row of A meet in the
+        // same L2.
+        const int64_t tiles = (int64_t)nt * nt;
+        const int64_t per = (tiles + 7) / 8;
+        idx = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+        if (idx >= tiles) return;
+        mode = 0;
+    } else {
+        mode = 1 + (int)blockIdx.y;
+        idx = blockIdx.x;
+    }
+    int64_t row0, col0;
+    if (!band_tile(mode, idx, n, b0, b1, nt, row0, col0)) return;
+    minplus_tile<U, ARGMIN, VEC>(D, NX, n, ld, K, BS, mode, row0, col0, sm);
+}
+
+// ------------------------------------------------------ persistent schedule
+// One launch runs every round (block size 128 = the tile edge).  Work items
+// are taken from per-round queues in round order; round K's items are, in
+// queue order: phase 1, the 2*nt phase-2 tiles (row band j, then column band
+// i), then the nt^2 phase-3 tiles, of which the ones round K+1's phases 1 and
+// 2 read (the diagonal tile of band K+1, then its row and column tiles) come
+// first.  Dependencies are epoch-valued flags (value = round + 1, so nothing
+// is reset between rounds), the GPU form of the per-block semaphores of the
+// paper's intra-round concurrency:
+//   phase 1 (K)        : tile (K, K) of round K-1 done            nrow[K] >= K
+//   phase 2 row tile j : phase 1 of round K                        diag >= K+1
+//                        tile (K, j) of round K-1 done            nrow[j] >= K
+//   phase 2 col tile i : phase 1 of round K,  tile (i, K) of K-1   ncol[i] >= K
+//   phase 3 tile (i,j) : every item of round K-1 done (its own C, and no
+//                        round-(K-1) reader of the old bands is left)
+//                        done[K-1] == items, rowf[j] >= K+1, colf[i] >= K+1
+// so phases 1 and 2 of round K+1 overlap the end of round K (the paper's
+// "inter-round" future work).  A workgroup waits only on items that running
+// workgroups have already taken, so the schedule needs no co-resident grid.
+// Flags are published with an agent-scope release (L2 write-back) and read
+// with an agent-scope acquire (L1/L2 invalidate), which is what makes a
+// tile written on one XCD visible on another.  Every wait is bounded by a
+// wall-clock deadline; on expiry the error word gets code 2 and an abort
+// flag makes every workgroup leave.
+struct PersistWs {
+    int *abort, *diag, *q, *xq, *done, *p2c, *rowf, *colf, *nrow, *ncol;
+};
+
+constexpr int kXcds = 8;        // MI355X: eight XCDs, workgroups dealt round-robin
+
+__host__ __device__ __forceinline__ int64_t persist_ws_ints(int R, int nt) {
+    return 4 + (3 + kXcds) * (int64_t)R + 4 * (int64_t)nt;
+}
+
+__device__ __forceinline__ PersistWs persist_ws(int *w, int R, int nt) {
+    PersistWs p;
+    p.abort = w;
+    p.diag = w + 1;
+    p.q = w + 4;
+    p.xq = p.q + R;
+    p.done = p.xq + (int64_t)kXcds * R;
+    p.p2c = p.done + R;
+    p.rowf = p.p2c + R;
+    p.colf = p.rowf + nt;
+    p.nrow = p.colf + nt;
+    p.ncol = p.nrow + nt;
+    return p;
+}
+
+__global__ void zero_ints_kernel(int *w, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        w[i] = 0;
+}
+
+__device__ __forceinline__ int ld_flag(const int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+// Thread 0 only.  Spins until *p >= v; false when the solve is aborted or the
+// deadline (s_memrealtime ticks) passes, which sets the error word and abort.
+__device__ bool wait_ge(const int *p, int v, const PersistWs &ws, int *err, uint64_t deadline) {
+    while (ld_flag(p) < v) {
+        if (ld_flag(ws.abort)) return false;
+        if (__builtin_amdgcn_s_memrealtime() > deadline) {
+            atomicCAS(err, 0, 2);
+            __hip_atomic_store(ws.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return true;
+}
+
+// Phase-3 queue position q of round K -> tile (ti, tj); nxt = K + 1 is the
+// next band, whose tiles come first.
+__device__ __forceinline__ void p3_tile(int64_t q, int nxt, int nt, int &ti, int &tj) {
+    if (nxt >= nt) {
+        ti = (int)(q / nt);
+        tj = (int)(q % nt);
+        return;
+    }
+    if (q == 0) {
+        ti = tj = nxt;
+        return;
+    }
+    q -= 1;
+    if (q < nt - 1) {
+        ti = nxt;
+        tj = (int)(q < nxt ? q : q + 1);
+        return;
+    }
+    q -= nt - 1;
+    if (q < nt - 1) {
+        tj = nxt;
+        ti = (int)(q < nxt ? q : q + 1);
+        return;
+    }
+    q -= nt - 1;
+    const int a = (int)(q / (nt - 1)), b = (int)(q % (nt - 1));
+    ti = a < nxt ? a : a + 1;
+    tj = b < nxt ? b : b + 1;
+}
+
+template <typename U, int ARGMIN> union PersistSmem {
+    MinplusSmem<U, ARGMIN> mp;
+    Phase1Smem<U, kTile, ARGMIN != 0> p1;      // successors in LDS
+};
+
+template <typename U, int ARGMIN, bool VEC>
+__global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 1 ? 1 : 4) void persistent_kernel(
+        U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int R, int nt,
+        int *__restrict__ wsp, int *__restrict__ err, uint64_t timeout_ticks) {
+    constexpr int NT = MinplusSmem<U, ARGMIN>::NT;
+    constexpr bool NEXT = ARGMIN != 0;
+    constexpr int BS = kTile;
+    __shared__ PersistSmem<U, ARGMIN> sm;
+    __shared__ int s_item, s_ok;
+    const PersistWs ws = persist_ws(wsp, R, nt);
+    const int items = 1 + 2 * nt + nt * nt;
+    const bool lead = threadIdx.x == 0;
+
+    // Phase-3 tiles other than the next band's are split into kXcds
+    // contiguous ranges; a workgroup drains the range of its own XCD first
+    // (tiles sharing a row of A then share an L2), then helps the others.
+    const int xcd = (int)(blockIdx.x % kXcds);
+    const int pq = (nt > 1) ? 2 * nt - 1 : 0;                 // next-band tiles (not in the last round)
+
+    for (int K = 0; K < R; ++K) {
+        const int64_t b0 = (int64_t)K * BS;
+        const int64_t b1 = b0 + imin64((int64_t)BS, n - b0);
+        const int pqk = (K + 1 < nt) ? pq : 0;
+        const int lim0 = 1 + 2 * nt + pqk;                     // items of the shared queue
+        const int rest = nt * nt - pqk;
+        const int per = (rest + kXcds - 1) / kXcds;
+        int mine = 0;            // items of round K taken by this workgroup
+        bool ready3 = false;     // every phase-3 dependency of round K acquired
+        // queue walk of thread 0: shared queue, then the XCD ranges
+        int stage = 0;
+        auto fetch = [&]() -> int {
+            if (stage == 0) {
+                const int v = __hip_atomic_fetch_add(&ws.q[K], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (v < lim0) return v;
+                stage = 1;
+            }
+            while (stage <= kXcds) {
+                const int x = (xcd + stage - 1) % kXcds;
+                const int tq = __hip_atomic_fetch_add(&ws.xq[(int64_t)K * kXcds + x], 1, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                const int pos = pqk + x * per + tq;
+                if (tq < per && pos < nt * nt) return 1 + 2 * nt + pos;
+                ++stage;
+            }
+            return items;
+        };
+        int upcoming = lead ? fetch() : 0;
+        for (;;) {
+            __syncthreads();
+            if (lead) s_item = upcoming;
+            __syncthreads();
+            const int item = s_item;
+            if (item >= items) break;
+            ++mine;
+            if (lead) upcoming = fetch();          // overlaps this item's work
+
+            // ---- what the item is
+            int mode = 0, ti = 0, tj = 0;        // mode: 0 phase 3, 1 row band, 2 column band
+            if (item > 0 && item <= 2 * nt) {
+                mode = item <= nt ? 1 : 2;
+                ti = tj = (item - 1) % nt;
+            } else if (item > 2 * nt) {
+                p3_tile(item - 1 - 2 * nt, K + 1, nt, ti, tj);
+            }
+            int64_t row0 = 0, col0 = 0;
+            const bool work = item > 0 &&
+                              band_tile(mode, mode == 0 ? (int64_t)ti * nt + tj : ti, n, b0, b1, nt, row0, col0);
+            const bool feeds = item > 2 * nt && (ti == K + 1 || tj == K + 1);   // read by round K+1's phases 1/2
+            // ---- wait for its inputs (one thread spins, then acquires)
+            const bool waits = item <= 2 * nt || (work && !ready3) || (!work && feeds);
+            if (waits) {
+                if (lead) {
+                    const uint64_t dl = __builtin_amdgcn_s_memrealtime() + timeout_ticks;
+                    int ok = 1;
+                    if (item == 0) {
+                        ok = K == 0 || wait_ge(&ws.nrow[K], K, ws, err, dl);
+                    } else if (item <= 2 * nt) {
+                        ok = wait_ge(ws.diag, K + 1, ws, err, dl);
+                        if (ok && K > 0) ok = wait_ge(mode == 1 ? &ws.nrow[tj] : &ws.ncol[ti], K, ws, err, dl);
+                    } else if (work) {
+                        ok = K == 0 || wait_ge(&ws.done[K - 1], items, ws, err, dl);
+                        // all of phase 2 done: nothing else to wait for in this round
+                        const bool all2 = ok && ld_flag(&ws.p2c[K]) >= 2 * nt;
+                        if (ok && !all2)
+                            ok = wait_ge(&ws.rowf[tj], K + 1, ws, err, dl) && wait_ge(&ws.colf[ti], K + 1, ws, err, dl);
+                        if (ok && all2) ok = 2;
+                    } else {
+                        // a band-K tile that round K+1 reads: its data come from
+                        // this round's phase 2; forward that tile's flag
+                        ok = (ti == K) ? wait_ge(&ws.rowf[tj], K + 1, ws, err, dl)
+                                       : wait_ge(&ws.colf[ti], K + 1, ws, err, dl);
+                    }
+                    s_ok = ok;
+                    acquire_agent();
+                }
+                __syncthreads();
+                if (!s_ok) return;
+                if (item > 2 * nt && work && s_ok == 2) ready3 = true;
+            }
+            // ---- the work
+            if (item == 0)
+                phase1_block<U, NEXT, BS, NT, NEXT>(D, NX, n, ld, K, sm.p1);
+            else if (work)
+                minplus_tile<U, ARGMIN, VEC>(D, NX, n, ld, K, BS, mode, row0, col0, sm.mp);
+            // ---- publish what later items wait for
+            if (item <= 2 * nt || feeds) {
+                __syncthreads();
+                if (lead) {
+                    release_agent();
+                    if (item == 0) {
+                        __hip_atomic_store(ws.diag, K + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    } else if (item <= 2 * nt) {
+                        __hip_atomic_store(mode == 1 ? &ws.rowf[tj] : &ws.colf[ti], K + 1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_fetch_add(&ws.p2c[K], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    } else {
+                        if (ti == K + 1) __hip_atomic_store(&ws.nrow[tj], K + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (tj == K + 1) __hip_atomic_store(&ws.ncol[ti], K + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+            }
+        }
+        // this workgroup's share of round K is finished
+        __syncthreads();
+        if (lead) {
+            release_agent();
+            __hip_atomic_fetch_add(&ws.done[K], mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (ld_flag(ws.abort)) return;
+    }
+}
+
 template <typename U>
 hipError_t init_t(const Plan &p) {
     dim3 grid((unsigned)((p.n + 255) / 256), (unsigned)imin64(p.n, 65535));
@@ -666,7 +985,47 @@ hipError_t minplus_v(const Plan &p, int K, int phase) {
     return p.vec ? minplus_t<U, ARGMIN, true>(p, K, phase) : minplus_t<U, ARGMIN, false>(p, K, phase);
 }
 
+template <typename U, int ARGMIN, bool VEC>
+hipError_t persistent_t(const Plan &p) {
+    constexpr int NT = (ARGMIN == 2) ? 512 : 256;
+    auto kern = persistent_kernel<U, ARGMIN, VEC>;
+    static int per_cu = -1;                    // resident workgroups per CU
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (per_cu < 0) {
+        int nb = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(kern), NT, 0);
+        if (e != hipSuccess) return e;
+        per_cu = nb > 0 ? nb : 1;
+    }
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const int64_t count = persist_ws_ints(p.rounds, p.nt);
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(8), dim3(256), 0, p.stream, p.work->persist, count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t items = 1 + 2 * (int64_t)p.nt + (int64_t)p.nt * p.nt;
+    const int grid = (int)imin64((int64_t)cus * per_cu, items);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), 0, p.stream, (U *)p.dist, p.next, p.n, p.ld, p.rounds, p.nt,
+                       p.work->persist, p.work->err, p.timeout_ticks);
+    return hipGetLastError();
+}
+
+template <typename U>
+hipError_t persistent_dispatch(const Plan &p) {
+    if (!p.next) return p.vec ? persistent_t<U, 0, true>(p) : persistent_t<U, 0, false>(p);
+    if (p.eager_argmin) return p.vec ? persistent_t<U, 1, true>(p) : persistent_t<U, 1, false>(p);
+    return p.vec ? persistent_t<U, 2, true>(p) : persistent_t<U, 2, false>(p);
+}
+
 }  // namespace
+
+int64_t persistent_workspace_ints(int rounds, int nt) { return persist_ws_ints(rounds, nt); }
+
+hipError_t launch_persistent(const Plan &p) {
+    return p.dtype == DType::I32 ? persistent_dispatch<uint32_t>(p) : persistent_dispatch<float>(p);
+}
 
 hipError_t launch_init(const Plan &p) {
     return p.dtype == DType::I32 ? init_t<uint32_t>(p) : init_t<float>(p);
