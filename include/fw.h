@@ -101,6 +101,25 @@ fw_status fw_solve_ex_i32(int32_t *dist, int32_t *next, int64_t n, int64_t ld,
 fw_status fw_solve_ex_f32(float *dist, int32_t *next, int64_t n, int64_t ld,
                           const fw_options *opt, void *stream);
 
+/* Batched solve: `batch` independent graphs in one launch (the batched
+ * configuration of the measurements; the paper solves one matrix at a time).
+ *   dist, next : one arena each; graph g is the n_g x n_g row-major block at
+ *                dist + d_offset[g] (and next + d_offset[g]; next may be NULL
+ *                for distances only); blocks must not overlap.
+ *   d_offset   : DEVICE array of batch int64 element offsets.
+ *   d_n        : DEVICE array of batch int32 sizes n_g (0 = empty graph).
+ *   n_max      : host bound on every n_g, 1 .. 65536; a graph with n_g < 0 or
+ *                n_g > n_max is skipped and fw_check reports
+ *                FW_ERR_INVALID_ARG.
+ *   opt        : NULL or options (block 0 or 128, validate, FW_FLAG_EAGER_ARGMIN).
+ * Each graph gets the same results as fw_solve_ex_* with block size 128.  The
+ * call enqueues two kernels and no allocation after the first call with a
+ * given (batch, n_max) size or smaller, so it can be captured in a hipGraph. */
+fw_status fw_solve_batched_i32(int32_t *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
+                               int32_t batch, int32_t n_max, const fw_options *opt, void *stream);
+fw_status fw_solve_batched_f32(float *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
+                               int32_t batch, int32_t n_max, const fw_options *opt, void *stream);
+
 /* Waits for `stream`, then returns (and clears) the first error the device
  * recorded for the current device since the last fw_check: FW_ERR_NEGATIVE,
  * FW_ERR_TIMEOUT, or FW_OK. */

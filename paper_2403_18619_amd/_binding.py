@@ -58,6 +58,10 @@ def _load():
         f = getattr(lib, name)
         f.argtypes = [vp, vp, i64, i64, opt_p, vp]
         f.restype = i32
+    for name in ("fw_solve_batched_i32", "fw_solve_batched_f32"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, vp, vp, vp, i32, i32, opt_p, vp]
+        f.restype = i32
     lib.fw_check.argtypes = [vp]
     lib.fw_check.restype = i32
     lib.fw_status_string.argtypes = [ctypes.c_int]
@@ -153,6 +157,35 @@ def solve(W, next_hop: bool = True, *, block: int = 0, schedule: int = 0,
     NX = torch.empty((n, ld), dtype=torch.int32, device=W.device)[:, :n] if next_hop else None
     solve_(D, NX, block=block, schedule=schedule, validate=validate, stream=stream, flags=flags)
     return D, NX
+
+
+def solve_batched_(dist, next, offsets, sizes, n_max: int, *, validate: bool = False,
+                   stream=None, flags: int = 0):
+    """In-place batched solve.  dist / next: 1-D device arenas (int32 or
+    float32 / int32); graph g is the sizes[g] x sizes[g] row-major block at
+    element offsets[g].  offsets (int64) and sizes (int32) are device tensors."""
+    import torch
+    for t, name in ((dist, "dist"), (offsets, "offsets"), (sizes, "sizes")):
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
+    if offsets.dtype != torch.int64 or sizes.dtype != torch.int32:
+        raise ValueError("offsets must be int64 and sizes int32")
+    if offsets.numel() != sizes.numel():
+        raise ValueError("offsets and sizes must have one entry per graph")
+    if dist.dtype == torch.int32:
+        fn = lib.fw_solve_batched_i32
+    elif dist.dtype == torch.float32:
+        fn = lib.fw_solve_batched_f32
+    else:
+        raise ValueError(f"dist dtype {dist.dtype} is not supported")
+    if next is not None and (next.dtype != torch.int32 or next.numel() < dist.numel()):
+        raise ValueError("next must be an int32 arena at least as large as dist")
+    opt = fw_options(0, 0, 1 if validate else 0, flags)
+    with torch.cuda.device(dist.device):
+        st = fn(dist.data_ptr(), None if next is None else next.data_ptr(), offsets.data_ptr(),
+                sizes.data_ptr(), sizes.numel(), int(n_max), ctypes.byref(opt), _stream_handle(stream))
+    _raise_if(st)
+    return dist, next
 
 
 def check(stream=None):

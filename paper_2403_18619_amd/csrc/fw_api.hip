@@ -101,25 +101,31 @@ hipError_t timed(bool on, int kind, hipStream_t st, F fn) {
     return hipSuccess;
 }
 
+// Grows a per-device int buffer to at least `need` entries (the old one is
+// freed, which waits for the device).
+fw_status grow_ints(int **buf, int64_t *cap, int64_t need, const char *what) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (*cap >= need) return FW_OK;
+    hipError_t e;
+    if (*buf) {
+        e = hipFree(*buf);
+        if (e != hipSuccess) return hip_fail(e, what);
+        *buf = nullptr;
+        *cap = 0;
+    }
+    e = hipMalloc(buf, need * sizeof(int));
+    if (e != hipSuccess) return hip_fail(e, what);
+    *cap = need;
+    return FW_OK;
+}
+
 // Persistent schedule: flag workspace of the right size (grown on demand;
 // the old one is freed, which waits for the device) and the wait bound.
 fw_status persistent_plan(fw::Plan &p, bool test_timeout) {
     const int64_t need = fw::persistent_workspace_ints(p.rounds, p.nt);
+    fw_status s = grow_ints(&p.work->persist, &p.work->persist_ints, need, "persistent workspace");
+    if (s != FW_OK) return s;
     hipError_t e;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        if (p.work->persist_ints < need) {
-            if (p.work->persist) {
-                e = hipFree(p.work->persist);
-                if (e != hipSuccess) return hip_fail(e, "hipFree(persistent workspace)");
-                p.work->persist = nullptr;
-                p.work->persist_ints = 0;
-            }
-            e = hipMalloc(&p.work->persist, need * sizeof(int));
-            if (e != hipSuccess) return hip_fail(e, "hipMalloc(persistent workspace)");
-            p.work->persist_ints = need;
-        }
-    }
     int dev = 0, khz = 0;
     e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
@@ -194,9 +200,57 @@ fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
     return FW_OK;
 }
 
+fw_status solve_batched(fw::DType dt, void *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
+                        int32_t batch, int32_t n_max, const fw_options *opt, void *stream) {
+    g_err[0] = 0;
+    if (batch < 0) return fail(FW_ERR_INVALID_ARG, "batch = %d is negative", batch);
+    if (batch == 0) return FW_OK;
+    if (!dist || !d_offset || !d_n) return fail(FW_ERR_INVALID_ARG, "dist, d_offset and d_n must not be NULL");
+    if (n_max < 1 || n_max > 65536)
+        return fail(FW_ERR_INVALID_ARG, "n_max = %d (allowed: 1 .. 65536)", n_max);
+    fw_options o = {0, FW_SCHED_AUTO, 0, 0};
+    if (opt) {
+        if (opt->flags & ~(FW_FLAG_EAGER_ARGMIN)) return fail(FW_ERR_INVALID_ARG, "flags = %d", opt->flags);
+        if (opt->block != 0 && opt->block != fw::kTile)
+            return fail(FW_ERR_UNSUPPORTED, "batched solves run block size %d only", fw::kTile);
+        o = *opt;
+    }
+    fw::DeviceWork *work = nullptr;
+    fw_status s = get_work(&work);
+    if (s != FW_OK) return s;
+    s = grow_ints(&work->batch, &work->batch_ints, (int64_t)n_max + 2 + batch, "batch workspace");
+    if (s != FW_OK) return s;
+    fw::BatchPlan b;
+    b.dtype = dt;
+    b.dist = dist;
+    b.next = next;
+    b.off = d_offset;
+    b.nv = d_n;
+    b.batch = batch;
+    b.n_max = n_max;
+    b.validate = o.validate != 0;
+    b.eager_argmin = (o.flags & FW_FLAG_EAGER_ARGMIN) != 0;
+    b.scratch = work->batch;
+    b.err = work->err;
+    b.stream = (hipStream_t)stream;
+    hipError_t e = fw::launch_batched(b);
+    if (e != hipSuccess) return hip_fail(e, "batched launch");
+    return FW_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+fw_status fw_solve_batched_i32(int32_t *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
+                               int32_t batch, int32_t n_max, const fw_options *opt, void *stream) {
+    return solve_batched(fw::DType::I32, dist, next, d_offset, d_n, batch, n_max, opt, stream);
+}
+
+fw_status fw_solve_batched_f32(float *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
+                               int32_t batch, int32_t n_max, const fw_options *opt, void *stream) {
+    return solve_batched(fw::DType::F32, dist, next, d_offset, d_n, batch, n_max, opt, stream);
+}
 
 fw_status fw_solve_i32(int32_t *dist, int32_t *next, int64_t n, int64_t ld, void *stream) {
     return solve(fw::DType::I32, dist, next, n, ld, nullptr, stream);
@@ -231,6 +285,7 @@ fw_status fw_check(void *stream) {
     if (e != hipSuccess) return hip_fail(e, "hipMemset(error word)");
     if (code == 1) return fail(FW_ERR_NEGATIVE, "a weight is negative or NaN");
     if (code == 2) return fail(FW_ERR_TIMEOUT, "a dependency wait exceeded its bound");
+    if (code == 3) return fail(FW_ERR_INVALID_ARG, "a batched graph has n < 0 or n > n_max");
     return fail(FW_ERR_HIP, "device error word %d", code);
 }
 

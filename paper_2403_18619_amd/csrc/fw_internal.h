@@ -16,6 +16,8 @@ struct DeviceWork {
     int *err = nullptr;        // device error word (0 = none)
     int *persist = nullptr;    // persistent-schedule flags and counters
     int64_t persist_ints = 0;  // their capacity
+    int *batch = nullptr;      // batched solve: graph order and counts
+    int64_t batch_ints = 0;    // its capacity
 };
 
 struct Plan {
@@ -34,6 +36,20 @@ struct Plan {
     DeviceWork *work;
 };
 
+// A batch of independent graphs (fw_solve_batched_*).
+struct BatchPlan {
+    DType dtype;
+    void *dist;
+    int32_t *next;             // may be null
+    const int64_t *off;        // device: first element of graph g
+    const int32_t *nv;         // device: vertices of graph g
+    int batch, n_max;
+    bool validate, eager_argmin;
+    int *scratch;              // n_max + 2 + batch ints (order and counts)
+    int *err;
+    hipStream_t stream;
+};
+
 // Enqueue helpers (fw_kernels.hip).  Each returns the launch's hipError_t.
 hipError_t launch_init(const Plan &p);
 hipError_t launch_phase1(const Plan &p, int K);
@@ -41,5 +57,6 @@ hipError_t launch_phase2(const Plan &p, int K);
 hipError_t launch_phase3(const Plan &p, int K);
 hipError_t launch_persistent(const Plan &p);
 int64_t persistent_workspace_ints(int rounds, int nt);
+hipError_t launch_batched(const BatchPlan &b);
 
 }  // namespace fw

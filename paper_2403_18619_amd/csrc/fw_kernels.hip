@@ -394,7 +394,6 @@ __device__ __forceinline__ void minplus_tile(U *__restrict__ D, int32_t *__restr
             for (int c = 0; c < CPT; ++c) idx[r][c] = -1;
     }
     if (ARGMIN == 2) {
-#pragma unroll
         for (int q = t; q < kTile * kTile / 4; q += NT) kst[q] = 0xFFFFFFFFu;
         for (int q = t; q < G::waves * 64; q += NT) qmin[q] = 0xFF;
     }
@@ -717,11 +716,17 @@ __global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 2 ? 4 : 1) void 
 //   phase 1 (K)        : tile (K, K) of round K-1 done            nrow[K] >= K
 //   phase 2 row tile j : phase 1 of round K                        diag >= K+1
 //                        tile (K, j) of round K-1 done            nrow[j] >= K
+//                        j = K-1 only: every round-(K-1) reader of
+//                        that tile (the phase-3 tiles (K, *)) done  rrd[K-1] >= nt-1
 //   phase 2 col tile i : phase 1 of round K,  tile (i, K) of K-1   ncol[i] >= K
+//                        i = K-1 only: the tiles (*, K) of K-1     crd[K-1] >= nt-1
 //   phase 3 tile (i,j) : every item of round K-1 done (its own C, and no
 //                        round-(K-1) reader of the old bands is left)
 //                        done[K-1] == items, rowf[j] >= K+1, colf[i] >= K+1
-// so phases 1 and 2 of round K+1 overlap the end of round K (the paper's
+// Tile (K, K-1) is both round K-1's column band -- the A operand of its
+// phase-3 tiles (K, *) -- and a tile that round K's row band overwrites, hence
+// the extra wait (write after read); likewise (K-1, K).  Phases 1 and 2 of
+// round K+1 thus overlap the end of round K (the paper's
 // "inter-round" future work).  A workgroup waits only on items that running
 // workgroups have already taken, so the schedule needs no co-resident grid.
 // Flags are published with an agent-scope release (L2 write-back) and read
@@ -730,13 +735,13 @@ __global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 2 ? 4 : 1) void 
 // wall-clock deadline; on expiry the error word gets code 2 and an abort
 // flag makes every workgroup leave.
 struct PersistWs {
-    int *abort, *diag, *q, *xq, *done, *p2c, *rowf, *colf, *nrow, *ncol;
+    int *abort, *diag, *q, *xq, *done, *p2c, *rrd, *crd, *rowf, *colf, *nrow, *ncol;
 };
 
 constexpr int kXcds = 8;        // MI355X: eight XCDs, workgroups dealt round-robin
 
 __host__ __device__ __forceinline__ int64_t persist_ws_ints(int R, int nt) {
-    return 4 + (3 + kXcds) * (int64_t)R + 4 * (int64_t)nt;
+    return 4 + (5 + kXcds) * (int64_t)R + 4 * (int64_t)nt;
 }
 
 __device__ __forceinline__ PersistWs persist_ws(int *w, int R, int nt) {
@@ -747,7 +752,9 @@ __device__ __forceinline__ PersistWs persist_ws(int *w, int R, int nt) {
     p.xq = p.q + R;
     p.done = p.xq + (int64_t)kXcds * R;
     p.p2c = p.done + R;
-    p.rowf = p.p2c + R;
+    p.rrd = p.p2c + R;
+    p.crd = p.rrd + R;
+    p.rowf = p.crd + R;
     p.colf = p.rowf + nt;
     p.nrow = p.colf + nt;
     p.ncol = p.nrow + nt;
@@ -764,6 +771,22 @@ __device__ __forceinline__ int ld_flag(const int *p) {
 }
 __device__ __forceinline__ void release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 __device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+// Waits until this wave's vector-memory operations (its global stores, a
+// cache invalidate) have completed.  A workgroup barrier alone does not: it
+// orders the waves but lets their stores still be on the way to L2.
+__device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Publishes everything the workgroup has written: every wave drains its
+// stores into L2, then one thread writes the L2 back (agent-scope release)
+// and stores the flag.
+__device__ __forceinline__ void publish(bool lead, int *flag, int value) {
+    wait_vmem();
+    __syncthreads();
+    if (lead) {
+        release_agent();
+        __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
 
 // Thread 0 only.  Spins until *p >= v; false when the solve is aborted or the
 // deadline (s_memrealtime ticks) passes, which sets the error word and abort.
@@ -894,6 +917,8 @@ __global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 1 ? 1 : 4) void 
                     } else if (item <= 2 * nt) {
                         ok = wait_ge(ws.diag, K + 1, ws, err, dl);
                         if (ok && K > 0) ok = wait_ge(mode == 1 ? &ws.nrow[tj] : &ws.ncol[ti], K, ws, err, dl);
+                        if (ok && K > 0 && ti == K - 1)
+                            ok = wait_ge(mode == 1 ? &ws.rrd[K - 1] : &ws.crd[K - 1], nt - 1, ws, err, dl);
                     } else if (work) {
                         ok = K == 0 || wait_ge(&ws.done[K - 1], items, ws, err, dl);
                         // all of phase 2 done: nothing else to wait for in this round
@@ -909,6 +934,7 @@ __global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 1 ? 1 : 4) void 
                     }
                     s_ok = ok;
                     acquire_agent();
+                    wait_vmem();
                 }
                 __syncthreads();
                 if (!s_ok) return;
@@ -920,30 +946,128 @@ __global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 1 ? 1 : 4) void 
             else if (work)
                 minplus_tile<U, ARGMIN, VEC>(D, NX, n, ld, K, BS, mode, row0, col0, sm.mp);
             // ---- publish what later items wait for
-            if (item <= 2 * nt || feeds) {
-                __syncthreads();
-                if (lead) {
-                    release_agent();
-                    if (item == 0) {
-                        __hip_atomic_store(ws.diag, K + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    } else if (item <= 2 * nt) {
-                        __hip_atomic_store(mode == 1 ? &ws.rowf[tj] : &ws.colf[ti], K + 1, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_fetch_add(&ws.p2c[K], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    } else {
-                        if (ti == K + 1) __hip_atomic_store(&ws.nrow[tj], K + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        if (tj == K + 1) __hip_atomic_store(&ws.ncol[ti], K + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
+            if (item == 0) {
+                publish(lead, ws.diag, K + 1);
+            } else if (item <= 2 * nt) {
+                publish(lead, mode == 1 ? &ws.rowf[tj] : &ws.colf[ti], K + 1);
+                if (lead) __hip_atomic_fetch_add(&ws.p2c[K], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else if (feeds) {
+                if (ti == K + 1) publish(lead, &ws.nrow[tj], K + 1);
+                if (tj == K + 1) publish(lead, &ws.ncol[ti], K + 1);
+                // a phase-3 tile of row (column) block K+1 has finished reading
+                // its band-K operand tile (K+1, K) (resp. (K, K+1))
+                if (work && lead) {
+                    if (ti == K + 1) __hip_atomic_fetch_add(&ws.rrd[K], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (tj == K + 1) __hip_atomic_fetch_add(&ws.crd[K], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
         }
         // this workgroup's share of round K is finished
+        wait_vmem();
         __syncthreads();
         if (lead) {
             release_agent();
             __hip_atomic_fetch_add(&ws.done[K], mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (ld_flag(ws.abort)) return;
+    }
+}
+
+// ------------------------------------------------------------- batched solve
+// Many independent graphs in one launch.  Graph g occupies an n_g x n_g
+// row-major block at dist + off[g] (and next + off[g]).  One workgroup solves
+// one graph: it normalises the input, then runs the blocked rounds itself --
+// phase 1 (phase1_block), the row and column bands and the remaining tiles
+// (minplus_tile) -- with workgroup barriers between the phases.  A graph of
+// at most 128 vertices is a single phase-1 closure.  Workgroups take graphs
+// in the order perm[] (largest first, from batch_order_kernel) so that the
+// largest graphs do not form the tail of the launch.
+template <typename U, int ARGMIN> union BatchSmem {
+    MinplusSmem<U, ARGMIN> mp;
+    Phase1Smem<U, kTile, false> p1;
+};
+
+// Counting sort of graph indices by decreasing n (one workgroup).  cnt must
+// hold n_max + 2 ints of scratch.
+__global__ __launch_bounds__(1024) void batch_order_kernel(const int32_t *__restrict__ nv, int batch, int n_max,
+                                                          int *__restrict__ cnt, int *__restrict__ perm,
+                                                          int *__restrict__ err) {
+    for (int v = threadIdx.x; v <= n_max + 1; v += blockDim.x) cnt[v] = 0;
+    __syncthreads();
+    for (int g = threadIdx.x; g < batch; g += blockDim.x) {
+        int m = nv[g];
+        if (m < 0 || m > n_max) {
+            atomicCAS(err, 0, 3);
+            m = 0;
+        }
+        atomicAdd(&cnt[n_max - m], 1);            // bucket 0 = largest n
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {                       // exclusive prefix sum (n_max is small)
+        int acc = 0;
+        for (int v = 0; v <= n_max; ++v) {
+            const int c = cnt[v];
+            cnt[v] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+    for (int g = threadIdx.x; g < batch; g += blockDim.x) {
+        int m = nv[g];
+        if (m < 0 || m > n_max) m = 0;
+        perm[atomicAdd(&cnt[n_max - m], 1)] = g;
+    }
+}
+
+template <typename U, int ARGMIN>
+__global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256) void batched_kernel(
+        U *__restrict__ D, int32_t *__restrict__ NX, const int64_t *__restrict__ off,
+        const int32_t *__restrict__ nv, const int *__restrict__ perm, int n_max, int validate,
+        int *__restrict__ err) {
+    constexpr int NT = MinplusSmem<U, ARGMIN>::NT;
+    constexpr bool NEXT = ARGMIN != 0;
+    constexpr int BS = kTile;
+    __shared__ BatchSmem<U, ARGMIN> sm;
+    const int g = perm[blockIdx.x];
+    const int64_t n = nv[g];
+    if (n <= 0 || n > n_max) return;               // reported by the ordering kernel
+    U *Dg = D + off[g];
+    int32_t *NXg = NEXT ? NX + off[g] : nullptr;
+    // normalise the input (as init_kernel), entries of this graph only
+    bool any_bad = false;
+    for (int64_t q = threadIdx.x; q < n * n; q += NT) {
+        const int64_t i = q / n, j = q % n;
+        bool bad;
+        const U w = norm_weight(Dg[q], i == j, bad);
+        any_bad |= bad;
+        Dg[q] = w;
+        if (NEXT) NXg[q] = (i == j) ? (int32_t)i : (w < Arith<U>::inf() ? (int32_t)j : -1);
+    }
+    if (validate && any_bad) atomicCAS(err, 0, 1);
+    __syncthreads();
+    const int R = (int)((n + BS - 1) / BS);
+    const int nt = R;
+    for (int K = 0; K < R; ++K) {
+        const int64_t b0 = (int64_t)K * BS;
+        const int64_t b1 = b0 + imin64((int64_t)BS, n - b0);
+        phase1_block<U, NEXT, BS, NT, false>(Dg, NXg, n, n, K, sm.p1);
+        __syncthreads();
+        if (R == 1) break;
+        for (int q = 0; q < 2 * nt; ++q) {          // row band, then column band
+            const int mode = q < nt ? 1 : 2;
+            int64_t row0, col0;
+            if (band_tile(mode, q % nt, n, b0, b1, nt, row0, col0)) {
+                minplus_tile<U, ARGMIN, false>(Dg, NXg, n, n, K, BS, mode, row0, col0, sm.mp);
+                __syncthreads();
+            }
+        }
+        for (int q = 0; q < nt * nt; ++q) {
+            int64_t row0, col0;
+            if (band_tile(0, q, n, b0, b1, nt, row0, col0)) {
+                minplus_tile<U, ARGMIN, false>(Dg, NXg, n, n, K, BS, 0, row0, col0, sm.mp);
+                __syncthreads();
+            }
+        }
     }
 }
 
@@ -1019,7 +1143,29 @@ hipError_t persistent_dispatch(const Plan &p) {
     return p.vec ? persistent_t<U, 2, true>(p) : persistent_t<U, 2, false>(p);
 }
 
+template <typename U, int ARGMIN>
+hipError_t batched_t(const BatchPlan &b) {
+    constexpr int NT = (ARGMIN == 2) ? 512 : 256;
+    hipLaunchKernelGGL(batch_order_kernel, dim3(1), dim3(1024), 0, b.stream, b.nv, b.batch, b.n_max, b.scratch,
+                       b.scratch + b.n_max + 2, b.err);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((batched_kernel<U, ARGMIN>), dim3((unsigned)b.batch), dim3(NT), 0, b.stream, (U *)b.dist,
+                       b.next, b.off, b.nv, b.scratch + b.n_max + 2, b.n_max, b.validate ? 1 : 0, b.err);
+    return hipGetLastError();
+}
+
+template <typename U>
+hipError_t batched_dispatch(const BatchPlan &b) {
+    if (!b.next) return batched_t<U, 0>(b);
+    return b.eager_argmin ? batched_t<U, 1>(b) : batched_t<U, 2>(b);
+}
+
 }  // namespace
+
+hipError_t launch_batched(const BatchPlan &b) {
+    return b.dtype == DType::I32 ? batched_dispatch<uint32_t>(b) : batched_dispatch<float>(b);
+}
 
 int64_t persistent_workspace_ints(int rounds, int nt) { return persist_ws_ints(rounds, nt); }
 

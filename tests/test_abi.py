@@ -12,7 +12,7 @@ def test_exports_every_header_symbol():
     syms = fw.header_symbols()
     assert {"fw_solve_i32", "fw_solve_f32", "fw_solve_ex_i32", "fw_solve_ex_f32",
             "fw_check", "fw_status_string", "fw_last_error", "fw_version",
-            "fw_phase_times"} <= set(syms)
+            "fw_phase_times", "fw_solve_batched_i32", "fw_solve_batched_f32"} <= set(syms)
     raw = ctypes.CDLL(fw.LIB_PATH)
     for s in syms:
         assert hasattr(raw, s), f"{s} declared in fw.h but not exported"
@@ -59,3 +59,16 @@ def test_python_binding_rejects_host_tensors():
     torch = pytest.importorskip("torch")
     with pytest.raises(ValueError):
         fw.solve(torch.zeros(4, 4, dtype=torch.int32))
+
+
+@pytest.mark.parametrize("fn", ["fw_solve_batched_i32", "fw_solve_batched_f32"])
+def test_batched_invalid_arguments_rejected_on_host(fn):
+    f = getattr(fw.lib, fn)
+    assert f(FAKE, None, FAKE, FAKE, -1, 16, None, None) == fw.FW_ERR_INVALID_ARG
+    assert f(None, None, FAKE, FAKE, 4, 16, None, None) == fw.FW_ERR_INVALID_ARG
+    assert f(FAKE, None, None, FAKE, 4, 16, None, None) == fw.FW_ERR_INVALID_ARG
+    assert f(FAKE, None, FAKE, FAKE, 4, 0, None, None) == fw.FW_ERR_INVALID_ARG
+    assert f(FAKE, None, FAKE, FAKE, 4, 1 << 20, None, None) == fw.FW_ERR_INVALID_ARG
+    opt = B.fw_options(64, 0, 0, 0)
+    assert f(FAKE, None, FAKE, FAKE, 4, 16, ctypes.byref(opt), None) == fw.FW_ERR_UNSUPPORTED
+    assert f(None, None, None, None, 0, 16, None, None) == fw.FW_OK
