@@ -120,6 +120,43 @@ fw_status fw_solve_batched_i32(int32_t *dist, int32_t *next, const int64_t *d_of
 fw_status fw_solve_batched_f32(float *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
                                int32_t batch, int32_t n_max, const fw_options *opt, void *stream);
 
+/* Gradient of the distances with respect to the edge weights, float32.
+ *
+ * After a solve with a successor matrix, every distance D[i][j] (i != j,
+ * reachable) is the sum of the weights along the selected path
+ * i -> next[i][j] -> next[next[i][j]][j] -> ... -> j.  Given the upstream
+ * gradient grad_dist = dL/dD of a loss L, this writes
+ *     grad_w[u][v] = sum of grad_dist[i][j] over the pairs (i, j), i != j,
+ *                    whose selected path uses the edge (u, v),
+ * which is dL/dW wherever the shortest paths are unique (elsewhere it is the
+ * gradient along the selected paths).  Diagonal entries, unreachable pairs
+ * and edges on no selected path get 0.  The weights themselves are not
+ * needed: the successor matrix carries the paths.
+ *
+ *  grad_dist : device, n x n at stride ld, read only
+ *  next      : device, n x n at stride ld, the successor matrix of the solve
+ *              (read only); an entry outside [0, n) counts as "no path" and
+ *              a successor cycle contributes nothing beyond it
+ *  grad_w    : device, n x n at stride ld, overwritten; must not overlap
+ *              grad_dist or next
+ * Entries are summed with float atomics, so the last bits can differ from
+ * run to run.  For n > 4096 the library keeps a scratch buffer of about
+ * 16 MiB per 1024 vertices (allocated on first use, kept until exit).
+ * Errors: FW_ERR_INVALID_ARG for n < 0, ld < n or NULL pointers. */
+fw_status fw_backward_f32(const float *grad_dist, const int32_t *next, float *grad_w, int64_t n, int64_t ld,
+                          void *stream);
+
+/* The same for a batch packed as for fw_solve_batched_*: graph g is the
+ * d_n[g] x d_n[g] row-major block at element d_offset[g] of grad_dist, next
+ * and grad_w.  d_offset / d_n are device arrays; n_max (host) bounds every
+ * d_n[g] and must be at most 4096 (FW_ERR_UNSUPPORTED otherwise); batch at
+ * most 65535.  A graph with d_n[g] outside [0, n_max] is skipped and
+ * reported by fw_check as FW_ERR_INVALID_ARG.  Enqueues a fixed sequence of
+ * kernels (no allocation), so it can be captured in a hipGraph. */
+fw_status fw_backward_batched_f32(const float *grad_dist, const int32_t *next, float *grad_w,
+                                  const int64_t *d_offset, const int32_t *d_n, int32_t batch, int32_t n_max,
+                                  void *stream);
+
 /* Waits for `stream`, then returns (and clears) the first error the device
  * recorded for the current device since the last fw_check: FW_ERR_NEGATIVE,
  * FW_ERR_TIMEOUT, or FW_OK. */

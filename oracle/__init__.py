@@ -6,8 +6,9 @@ leg may import this package.  It shares no code with the GPU library
 
 ``fw_oracle.c`` is the plain Floyd-Warshall triple loop (Section 2.3, Fig. 1
 of the paper), with a strict comparison and a successor ("next hop") matrix;
-``validate.c`` checks any distance / next-hop pair by walking paths.
-``grad_ref`` is the plain definition of the shortest-path gradient.
+``validate.c`` checks any distance / next-hop pair by walking paths;
+``grad.c`` is the plain definition of the shortest-path gradient (every
+selected path walked, its upstream value added to each edge on it).
 """
 from __future__ import annotations
 
@@ -19,7 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRCS = [os.path.join(_HERE, "fw_oracle.c"), os.path.join(_HERE, "validate.c")]
+_SRCS = [os.path.join(_HERE, "fw_oracle.c"), os.path.join(_HERE, "validate.c"), os.path.join(_HERE, "grad.c")]
 
 INF_I32 = 1 << 30
 
@@ -49,6 +50,8 @@ def load_library(path: str = _SO):
     lib.validate_walk_i32.restype = i64
     lib.validate_walk_f32.argtypes = [vp, i64, vp, vp, i64, i64, vp, i64, dbl, vp]
     lib.validate_walk_f32.restype = i64
+    lib.oracle_grad_f64.argtypes = [vp, i64, vp, i64, i64, vp, i64]
+    lib.oracle_grad_f64.restype = i64
     return lib
 
 
@@ -165,20 +168,22 @@ def triangle_violations(D, ks=None):
     return bad
 
 
-def grad_ref(G, NX, W=None):
-    """dL/dW for L = sum(G * D), by its plain definition: every pair (i, j)
-    with i != j and a path adds G[i][j] to each edge on the path that the
-    successor matrix NX selects.  Float64 result."""
+def grad_ref(G, NX, lib=None):
+    """dL/dW for L = sum(G * D): every pair (i, j), i != j, with a path adds
+    G[i][j] to each edge of the path that the successor matrix NX selects.
+    Float64 result; raises if a walk is broken."""
+    lib = lib or _L()
+    G = np.ascontiguousarray(G, np.float32)
+    NX = np.ascontiguousarray(NX, np.int32)
     n = NX.shape[0]
-    out = np.zeros((n, n), np.float64)
-    for i in range(n):
-        for j in range(n):
-            if i == j or NX[i, j] < 0:
-                continue
-            g = float(G[i, j])
-            u = i
-            while u != j:
-                h = int(NX[u, j])
-                out[u, h] += g
-                u = h
+    out = np.empty((n, n), np.float64)
+    bad = lib.oracle_grad_f64(G.ctypes.data, G.shape[1], NX.ctypes.data, NX.shape[1], n,
+                              out.ctypes.data, n)
+    if bad:
+        raise ValueError(f"{bad} successor walks are broken")
     return out
+
+
+def grad_abs_ref(G, NX, lib=None):
+    """The same sums over |G|: the scale of each gradient entry's rounding."""
+    return grad_ref(np.abs(np.asarray(G, np.float32)), NX, lib=lib)

@@ -62,6 +62,10 @@ def _load():
         f = getattr(lib, name)
         f.argtypes = [vp, vp, vp, vp, i32, i32, opt_p, vp]
         f.restype = i32
+    lib.fw_backward_f32.argtypes = [vp, vp, vp, i64, i64, vp]
+    lib.fw_backward_f32.restype = i32
+    lib.fw_backward_batched_f32.argtypes = [vp, vp, vp, vp, vp, i32, i32, vp]
+    lib.fw_backward_batched_f32.restype = i32
     lib.fw_check.argtypes = [vp]
     lib.fw_check.restype = i32
     lib.fw_status_string.argtypes = [ctypes.c_int]
@@ -186,6 +190,49 @@ def solve_batched_(dist, next, offsets, sizes, n_max: int, *, validate: bool = F
                 sizes.data_ptr(), sizes.numel(), int(n_max), ctypes.byref(opt), _stream_handle(stream))
     _raise_if(st)
     return dist, next
+
+
+def backward_(grad_dist, next, grad_w, *, stream=None):
+    """grad_w <- gradient of the distances with respect to the edge weights
+    along the paths of the successor matrix ``next`` (fw_backward_f32).  All
+    three are n x n device tensors with the same strides; grad_w is
+    overwritten."""
+    import torch
+    n, ld = _check_matrix(grad_dist, "grad_dist")
+    if grad_dist.dtype != torch.float32 or grad_w.dtype != torch.float32:
+        raise ValueError("grad_dist and grad_w must be float32")
+    if next.dtype != torch.int32:
+        raise ValueError("next must be int32")
+    for t, name in ((next, "next"), (grad_w, "grad_w")):
+        if t.shape != grad_dist.shape or (n and t.stride() != grad_dist.stride()) or t.device != grad_dist.device:
+            raise ValueError(f"{name} must have the shape, strides and device of grad_dist")
+    with torch.cuda.device(grad_dist.device):
+        st = lib.fw_backward_f32(grad_dist.data_ptr(), next.data_ptr(), grad_w.data_ptr(), n, ld,
+                                 _stream_handle(stream))
+    _raise_if(st)
+    return grad_w
+
+
+def backward_batched_(grad_dist, next, grad_w, offsets, sizes, n_max: int, *, stream=None):
+    """Batched fw_backward: 1-D float32 / int32 / float32 arenas packed as for
+    solve_batched_ (graph g: sizes[g] x sizes[g] at element offsets[g])."""
+    import torch
+    for t, name in ((grad_dist, "grad_dist"), (next, "next"), (grad_w, "grad_w"), (offsets, "offsets"),
+                    (sizes, "sizes")):
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
+    if grad_dist.dtype != torch.float32 or grad_w.dtype != torch.float32 or next.dtype != torch.int32:
+        raise ValueError("grad_dist / grad_w must be float32 and next int32")
+    if offsets.dtype != torch.int64 or sizes.dtype != torch.int32 or offsets.numel() != sizes.numel():
+        raise ValueError("offsets (int64) and sizes (int32) must have one entry per graph")
+    if next.numel() < grad_dist.numel() or grad_w.numel() < grad_dist.numel():
+        raise ValueError("next and grad_w must be at least as large as grad_dist")
+    with torch.cuda.device(grad_dist.device):
+        st = lib.fw_backward_batched_f32(grad_dist.data_ptr(), next.data_ptr(), grad_w.data_ptr(),
+                                         offsets.data_ptr(), sizes.data_ptr(), sizes.numel(), int(n_max),
+                                         _stream_handle(stream))
+    _raise_if(st)
+    return grad_w
 
 
 def check(stream=None):

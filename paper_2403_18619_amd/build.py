@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 SO = os.path.join(PKG, "libfwgpu.so")
-SOURCES = ["fw_kernels.hip", "fw_api.hip"]
+SOURCES = ["fw_kernels.hip", "fw_backward.hip", "fw_api.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

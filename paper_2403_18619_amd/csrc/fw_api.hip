@@ -238,9 +238,65 @@ fw_status solve_batched(fw::DType dt, void *dist, int32_t *next, const int64_t *
     return FW_OK;
 }
 
+fw_status backward(const float *G, const int32_t *next, float *dW, int64_t n, int64_t ld, const int64_t *d_offset,
+                   const int32_t *d_n, int32_t batch, int32_t n_max, void *stream) {
+    g_err[0] = 0;
+    fw::BackwardPlan b;
+    b.G = G;
+    b.NX = next;
+    b.dW = dW;
+    b.n = n;
+    b.ld = ld;
+    b.off = d_offset;
+    b.nv = d_n;
+    b.batch = batch;
+    b.scratch = nullptr;
+    b.stream = (hipStream_t)stream;
+    if (!d_offset) {                           // one graph
+        fw_status s = check_args(G, n, ld, nullptr);
+        if (s != FW_OK || n == 0) return s;
+        if (!next || !dW) return fail(FW_ERR_INVALID_ARG, "next and grad_w must not be NULL");
+        b.n_cap = (int)n;
+    } else {
+        if (batch < 0) return fail(FW_ERR_INVALID_ARG, "batch = %d is negative", batch);
+        if (batch == 0) return FW_OK;
+        if (batch > 65535) return fail(FW_ERR_UNSUPPORTED, "batch = %d (at most 65535 graphs per call)", batch);
+        if (!G || !next || !dW || !d_n) return fail(FW_ERR_INVALID_ARG, "pointer arguments must not be NULL");
+        if (n_max < 1 || n_max > fw::kBackwardLdsMaxN)
+            return fail(n_max < 1 ? FW_ERR_INVALID_ARG : FW_ERR_UNSUPPORTED,
+                        "n_max = %d (batched gradients: 1 .. %d)", n_max, fw::kBackwardLdsMaxN);
+        b.n_cap = n_max;
+    }
+    fw::DeviceWork *work = nullptr;
+    fw_status s = get_work(&work);
+    if (s != FW_OK) return s;
+    b.err = work->err;
+    const int64_t need = fw::backward_scratch_ints(b);
+    if (need > 0) {
+        s = grow_ints(&work->bwd, &work->bwd_ints, need, "backward workspace");
+        if (s != FW_OK) return s;
+        b.scratch = work->bwd;
+    }
+    hipError_t e = fw::launch_backward(b);
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
+    return FW_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+fw_status fw_backward_f32(const float *grad_dist, const int32_t *next, float *grad_w, int64_t n, int64_t ld,
+                          void *stream) {
+    return backward(grad_dist, next, grad_w, n, ld, nullptr, nullptr, 0, 0, stream);
+}
+
+fw_status fw_backward_batched_f32(const float *grad_dist, const int32_t *next, float *grad_w,
+                                  const int64_t *d_offset, const int32_t *d_n, int32_t batch, int32_t n_max,
+                                  void *stream) {
+    if (!d_offset && batch > 0) return fail(FW_ERR_INVALID_ARG, "d_offset must not be NULL");
+    return backward(grad_dist, next, grad_w, 0, 0, d_offset, d_n, batch, n_max, stream);
+}
 
 fw_status fw_solve_batched_i32(int32_t *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
                                int32_t batch, int32_t n_max, const fw_options *opt, void *stream) {

@@ -18,6 +18,8 @@ struct DeviceWork {
     int64_t persist_ints = 0;  // their capacity
     int *batch = nullptr;      // batched solve: graph order and counts
     int64_t batch_ints = 0;    // its capacity
+    int *bwd = nullptr;        // backward, large n: per-workgroup vertex arrays
+    int64_t bwd_ints = 0;      // its capacity
 };
 
 struct Plan {
@@ -49,6 +51,26 @@ struct BatchPlan {
     int *err;
     hipStream_t stream;
 };
+
+// Gradient pass (fw_backward.hip): one graph (off == nullptr: n x n at
+// stride ld) or a batch packed like the batched solve (row stride n).
+constexpr int kBackwardLdsMaxN = 4096;   // per-destination arrays in LDS (16 bytes per vertex)
+struct BackwardPlan {
+    const float *G;
+    const int32_t *NX;
+    float *dW;
+    int64_t n, ld;             // single graph
+    const int64_t *off;        // batch: device offsets (nullptr for one graph)
+    const int32_t *nv;         // batch: device sizes
+    int batch;
+    int n_cap;                 // largest n (single graph: n)
+    int *scratch;              // n_cap > kBackwardLdsMaxN: backward_scratch_ints ints
+    int *err;
+    hipStream_t stream;
+};
+hipError_t launch_backward(const BackwardPlan &b);
+int64_t backward_scratch_ints(const BackwardPlan &b);
+int backward_global_workgroups(const BackwardPlan &b);
 
 // Enqueue helpers (fw_kernels.hip).  Each returns the launch's hipError_t.
 hipError_t launch_init(const Plan &p);

@@ -12,7 +12,8 @@ def test_exports_every_header_symbol():
     syms = fw.header_symbols()
     assert {"fw_solve_i32", "fw_solve_f32", "fw_solve_ex_i32", "fw_solve_ex_f32",
             "fw_check", "fw_status_string", "fw_last_error", "fw_version",
-            "fw_phase_times", "fw_solve_batched_i32", "fw_solve_batched_f32"} <= set(syms)
+            "fw_phase_times", "fw_solve_batched_i32", "fw_solve_batched_f32",
+            "fw_backward_f32", "fw_backward_batched_f32"} <= set(syms)
     raw = ctypes.CDLL(fw.LIB_PATH)
     for s in syms:
         assert hasattr(raw, s), f"{s} declared in fw.h but not exported"
@@ -72,3 +73,22 @@ def test_batched_invalid_arguments_rejected_on_host(fn):
     opt = B.fw_options(64, 0, 0, 0)
     assert f(FAKE, None, FAKE, FAKE, 4, 16, ctypes.byref(opt), None) == fw.FW_ERR_UNSUPPORTED
     assert f(None, None, None, None, 0, 16, None, None) == fw.FW_OK
+
+
+def test_backward_invalid_arguments_rejected_on_host():
+    f = fw.lib.fw_backward_f32
+    assert f(FAKE, FAKE, FAKE, -1, 4, None) == fw.FW_ERR_INVALID_ARG
+    assert f(FAKE, FAKE, FAKE, 8, 7, None) == fw.FW_ERR_INVALID_ARG
+    assert f(None, FAKE, FAKE, 4, 4, None) == fw.FW_ERR_INVALID_ARG
+    assert f(FAKE, None, FAKE, 4, 4, None) == fw.FW_ERR_INVALID_ARG
+    assert f(FAKE, FAKE, None, 4, 4, None) == fw.FW_ERR_INVALID_ARG
+    assert f(None, None, None, 0, 0, None) == fw.FW_OK
+    g = fw.lib.fw_backward_batched_f32
+    assert g(FAKE, FAKE, FAKE, FAKE, FAKE, -1, 16, None) == fw.FW_ERR_INVALID_ARG
+    assert g(FAKE, FAKE, FAKE, None, FAKE, 4, 16, None) == fw.FW_ERR_INVALID_ARG
+    assert g(FAKE, None, FAKE, FAKE, FAKE, 4, 16, None) == fw.FW_ERR_INVALID_ARG
+    assert g(FAKE, FAKE, FAKE, FAKE, FAKE, 4, 0, None) == fw.FW_ERR_INVALID_ARG
+    assert g(FAKE, FAKE, FAKE, FAKE, FAKE, 4, 4097, None) == fw.FW_ERR_UNSUPPORTED
+    assert "4096" in fw.last_error()
+    assert g(FAKE, FAKE, FAKE, FAKE, FAKE, 70000, 16, None) == fw.FW_ERR_UNSUPPORTED
+    assert g(None, None, None, None, None, 0, 16, None) == fw.FW_OK

@@ -20,6 +20,7 @@ from tests.test_oracle import check_all_pins_i32
 INF = P.INF
 SRC = os.path.join(os.path.dirname(oracle.__file__), "fw_oracle.c")
 VAL = os.path.join(os.path.dirname(oracle.__file__), "validate.c")
+GRAD = os.path.join(os.path.dirname(oracle.__file__), "grad.c")
 
 MUTANTS = {
     "non-strict compare (Fig. 1 as printed)": ("if (s < (int64_t)Di[j])", "if (s <= (int64_t)Di[j])"),
@@ -65,7 +66,7 @@ def test_mutant_is_caught(name, tmp_path):
     cfile.write_text(mutated)
     so = tmp_path / "libmut.so"
     subprocess.check_call(["gcc", "-O1", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-                           str(cfile), VAL, "-o", str(so), "-lm"])
+                           str(cfile), VAL, GRAD, "-o", str(so), "-lm"])
     lib = oracle.load_library(str(so))
     caught = []
     for W in graphs():
