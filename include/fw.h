@@ -73,6 +73,9 @@ typedef struct fw_options {
     int32_t validate;  /* non-zero: the device checks every weight (>= 0,
                           not NaN) and fw_check() reports FW_ERR_NEGATIVE  */
     int32_t flags;     /* 0, or FW_FLAG_* bits below                       */
+    int32_t team;      /* batched solves: most workgroups that share one
+                          graph; 0 = automatic, 1 = one workgroup solves a
+                          whole graph (ignored by single solves)           */
 } fw_options;
 
 /* fw_options.flags: record a pair of HIP events on the solve's stream around
@@ -111,14 +114,54 @@ fw_status fw_solve_ex_f32(float *dist, int32_t *next, int64_t n, int64_t ld,
  *   n_max      : host bound on every n_g, 1 .. 65536; a graph with n_g < 0 or
  *                n_g > n_max is skipped and fw_check reports
  *                FW_ERR_INVALID_ARG.
- *   opt        : NULL or options (block 0 or 128, validate, FW_FLAG_EAGER_ARGMIN).
+ *   opt        : NULL or options (block 0 or 128, validate, team,
+ *                FW_FLAG_EAGER_ARGMIN).
+ * Graphs are taken largest first.  With team == 1 one workgroup solves each
+ * graph; otherwise a graph of nt = ceil(n_g / 128) tiles per side is shared
+ * by a team of up to min(nt^2, team) workgroups that run the persistent
+ * schedule (per-tile flags, dependency waits bounded as for single solves:
+ * FW_ERR_TIMEOUT from fw_check).  team == 0 takes the limit from the tuned
+ * table that fw_tune_batched_* filled for this data type, successor choice
+ * and nt of n_max, else 1 when nt <= 2 and 2 nt above.
  * Each graph gets the same results as fw_solve_ex_* with block size 128.  The
- * call enqueues two kernels and no allocation after the first call with a
- * given (batch, n_max) size or smaller, so it can be captured in a hipGraph. */
+ * call enqueues at most four kernels and no allocation after the first call
+ * with a given (batch, n_max, team) size or smaller, so it can be captured in
+ * a hipGraph. */
 fw_status fw_solve_batched_i32(int32_t *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
                                int32_t batch, int32_t n_max, const fw_options *opt, void *stream);
 fw_status fw_solve_batched_f32(float *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
                                int32_t batch, int32_t n_max, const fw_options *opt, void *stream);
+
+/* Autotuners.  Each times its candidate configurations on the caller's own
+ * input -- dist is copied to a scratch buffer first and restored before every
+ * run and on return, so dist still holds its input afterwards (next holds the
+ * last run's output) -- and records the fastest in a per-process table that
+ * the automatic choices (block 0 with FW_SCHED_AUTO; team 0) consult for the
+ * same data type, successor choice and size.  Each call synchronises
+ * `stream`, allocates and frees a scratch copy of dist, and takes about
+ * (candidates x (reps + 1)) solves.  Not for use under hipGraph capture.
+ *
+ * fw_tune_solve_*: candidates block 32, 64, 128 with three launches per
+ * round, and the persistent schedule; the table key is (dtype, next != NULL,
+ * n).  Arguments as fw_solve_ex_*; reps >= 1 timed runs per candidate;
+ * outputs (host, may be NULL): the winning block, schedule and its mean
+ * milliseconds. */
+fw_status fw_tune_solve_i32(int32_t *dist, int32_t *next, int64_t n, int64_t ld, int32_t reps, int32_t *best_block,
+                            int32_t *best_schedule, double *best_ms, void *stream);
+fw_status fw_tune_solve_f32(float *dist, int32_t *next, int64_t n, int64_t ld, int32_t reps, int32_t *best_block,
+                            int32_t *best_schedule, double *best_ms, void *stream);
+
+/* fw_tune_batched_*: candidates team = 1, 2, 4, ... up to nt^2 (nt = tiles
+ * per side of an n_max graph); the table key is (dtype, next != NULL, nt).
+ * Arguments as fw_solve_batched_*, plus elems = number of elements of the
+ * dist arena to restore (covering every graph) and reps as above; outputs:
+ * the winning team limit and its mean milliseconds. */
+fw_status fw_tune_batched_i32(int32_t *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
+                              int32_t batch, int32_t n_max, int64_t elems, int32_t reps, int32_t *best_team,
+                              double *best_ms, void *stream);
+fw_status fw_tune_batched_f32(float *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
+                              int32_t batch, int32_t n_max, int64_t elems, int32_t reps, int32_t *best_team,
+                              double *best_ms, void *stream);
 
 /* Gradient of the distances with respect to the edge weights, float32.
  *

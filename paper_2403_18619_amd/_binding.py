@@ -31,7 +31,7 @@ PHASE_KINDS = ("init", "phase1", "phase2", "phase3", "persistent")
 
 class fw_options(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("validate", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("validate", ctypes.c_int32), ("flags", ctypes.c_int32), ("team", ctypes.c_int32)]
 
 
 class FwError(RuntimeError):
@@ -66,6 +66,15 @@ def _load():
     lib.fw_backward_f32.restype = i32
     lib.fw_backward_batched_f32.argtypes = [vp, vp, vp, vp, vp, i32, i32, vp]
     lib.fw_backward_batched_f32.restype = i32
+    for name in ("fw_tune_batched_i32", "fw_tune_batched_f32"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, vp, vp, vp, i32, i32, i64, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double), vp]
+        f.restype = i32
+    for name in ("fw_tune_solve_i32", "fw_tune_solve_f32"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, vp, i64, i64, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                      ctypes.POINTER(ctypes.c_double), vp]
+        f.restype = i32
     lib.fw_check.argtypes = [vp]
     lib.fw_check.restype = i32
     lib.fw_status_string.argtypes = [ctypes.c_int]
@@ -141,7 +150,7 @@ def solve_(dist, next=None, *, block: int = 0, schedule: int = 0, validate: bool
         if next.device != dist.device:
             raise ValueError("next must be on the same device as dist")
         nptr = next.data_ptr()
-    opt = fw_options(block, schedule, 1 if validate else 0, flags)
+    opt = fw_options(block, schedule, 1 if validate else 0, flags, 0)
     with torch.cuda.device(dist.device):
         st = fn(dist.data_ptr(), nptr, n, ld, ctypes.byref(opt), _stream_handle(stream))
     _raise_if(st)
@@ -164,7 +173,7 @@ def solve(W, next_hop: bool = True, *, block: int = 0, schedule: int = 0,
 
 
 def solve_batched_(dist, next, offsets, sizes, n_max: int, *, validate: bool = False,
-                   stream=None, flags: int = 0):
+                   stream=None, flags: int = 0, team: int = 0):
     """In-place batched solve.  dist / next: 1-D device arenas (int32 or
     float32 / int32); graph g is the sizes[g] x sizes[g] row-major block at
     element offsets[g].  offsets (int64) and sizes (int32) are device tensors."""
@@ -184,7 +193,7 @@ def solve_batched_(dist, next, offsets, sizes, n_max: int, *, validate: bool = F
         raise ValueError(f"dist dtype {dist.dtype} is not supported")
     if next is not None and (next.dtype != torch.int32 or next.numel() < dist.numel()):
         raise ValueError("next must be an int32 arena at least as large as dist")
-    opt = fw_options(0, 0, 1 if validate else 0, flags)
+    opt = fw_options(0, 0, 1 if validate else 0, flags, team)
     with torch.cuda.device(dist.device):
         st = fn(dist.data_ptr(), None if next is None else next.data_ptr(), offsets.data_ptr(),
                 sizes.data_ptr(), sizes.numel(), int(n_max), ctypes.byref(opt), _stream_handle(stream))
@@ -233,6 +242,51 @@ def backward_batched_(grad_dist, next, grad_w, offsets, sizes, n_max: int, *, st
                                          _stream_handle(stream))
     _raise_if(st)
     return grad_w
+
+
+def tune_solve_(dist, next=None, *, reps: int = 2, stream=None):
+    """Autotune the block size and schedule of single solves of this size on
+    this input (fw_tune_solve_*).  dist keeps its input contents.  Returns
+    (block, schedule, mean_ms); later solves with block=0 and the automatic
+    schedule use the winner."""
+    import torch
+    n, ld = _check_matrix(dist, "dist")
+    fn = {torch.int32: lib.fw_tune_solve_i32, torch.float32: lib.fw_tune_solve_f32}.get(dist.dtype)
+    if fn is None:
+        raise ValueError(f"dist dtype {dist.dtype} is not supported")
+    if next is not None and (next.dtype != torch.int32 or next.shape != dist.shape or
+                             (n and next.stride() != dist.stride())):
+        raise ValueError("next must be int32 with the same shape and strides as dist")
+    bb, bs, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0)
+    with torch.cuda.device(dist.device):
+        st = fn(dist.data_ptr(), None if next is None else next.data_ptr(), n, ld, reps, ctypes.byref(bb),
+                ctypes.byref(bs), ctypes.byref(ms), _stream_handle(stream))
+    _raise_if(st)
+    return bb.value, bs.value, ms.value
+
+
+def tune_batched_(dist, next, offsets, sizes, n_max: int, *, reps: int = 2, stream=None):
+    """Autotune the team limit of batched solves of this batch
+    (fw_tune_batched_*).  dist keeps its input contents.  Returns (team,
+    mean_ms); later batched solves with team=0 use the winner."""
+    import torch
+    fn = {torch.int32: lib.fw_tune_batched_i32, torch.float32: lib.fw_tune_batched_f32}.get(dist.dtype)
+    if fn is None:
+        raise ValueError(f"dist dtype {dist.dtype} is not supported")
+    for t, name in ((dist, "dist"), (offsets, "offsets"), (sizes, "sizes")):
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
+    if offsets.dtype != torch.int64 or sizes.dtype != torch.int32 or offsets.numel() != sizes.numel():
+        raise ValueError("offsets (int64) and sizes (int32) must have one entry per graph")
+    if next is not None and (next.dtype != torch.int32 or next.numel() < dist.numel()):
+        raise ValueError("next must be an int32 arena at least as large as dist")
+    team, ms = ctypes.c_int32(0), ctypes.c_double(0)
+    with torch.cuda.device(dist.device):
+        st = fn(dist.data_ptr(), None if next is None else next.data_ptr(), offsets.data_ptr(), sizes.data_ptr(),
+                sizes.numel(), int(n_max), dist.numel(), reps, ctypes.byref(team), ctypes.byref(ms),
+                _stream_handle(stream))
+    _raise_if(st)
+    return team.value, ms.value
 
 
 def check(stream=None):

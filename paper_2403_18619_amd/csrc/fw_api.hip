@@ -121,20 +121,35 @@ fw_status grow_ints(int **buf, int64_t *cap, int64_t need, const char *what) {
 
 // Persistent schedule: flag workspace of the right size (grown on demand;
 // the old one is freed, which waits for the device) and the wait bound.
+fw_status wait_bound(bool test_timeout, uint64_t *ticks);
+
 fw_status persistent_plan(fw::Plan &p, bool test_timeout) {
     const int64_t need = fw::persistent_workspace_ints(p.rounds, p.nt);
     fw_status s = grow_ints(&p.work->persist, &p.work->persist_ints, need, "persistent workspace");
     if (s != FW_OK) return s;
-    hipError_t e;
-    int dev = 0, khz = 0;
-    e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
-    if (e != hipSuccess) return hip_fail(e, "wall clock rate");
-    if (khz <= 0) khz = 100000;
-    // a wait never legitimately lasts longer than a few rounds; 20 s is far
-    // beyond that and still ends a stuck solve
-    p.timeout_ticks = test_timeout ? 0 : (uint64_t)khz * 1000ull * 20ull;
-    return FW_OK;
+    return wait_bound(test_timeout, &p.timeout_ticks);
+}
+
+// ---- tuned team limits for batched solves (fw_tune_batched)
+std::mutex g_tune_mu;
+std::unordered_map<int64_t, int> g_tuned;
+int64_t tune_key(fw::DType dt, bool next, int nt) {
+    return ((int64_t)nt << 2) | ((int64_t)(dt == fw::DType::F32) << 1) | (int64_t)next;
+}
+int tuned_team(fw::DType dt, bool next, int nt) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(tune_key(dt, next, nt));
+    return it == g_tuned.end() ? 0 : it->second;
+}
+// single solves: (block << 8) | schedule per (dtype, successors, n)
+std::unordered_map<int64_t, int> g_tuned_solve;
+int64_t solve_key(fw::DType dt, bool next, int64_t n) {
+    return (n << 2) | ((int64_t)(dt == fw::DType::F32) << 1) | (int64_t)next;
+}
+int tuned_solve(fw::DType dt, bool next, int64_t n) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned_solve.find(solve_key(dt, next, n));
+    return it == g_tuned_solve.end() ? 0 : it->second;
 }
 
 int auto_block(int64_t n) {
@@ -148,11 +163,18 @@ fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
     g_err[0] = 0;
     fw_status s = check_args(dist, n, ld, opt);
     if (s != FW_OK || n == 0) return s;
-    fw_options o = {0, FW_SCHED_AUTO, 0, 0};
+    fw_options o = {0, FW_SCHED_AUTO, 0, 0, 0};
     if (opt) o = *opt;
     // Automatic schedule (measured on MI355X): one persistent launch hides
     // phase 1 and 2 behind the previous round and removes launch gaps; only
     // large solves with successors run slightly faster as three launches.
+    if (o.schedule == FW_SCHED_AUTO && o.block == 0) {        // a tuned choice for this size, if any
+        const int t = tuned_solve(dt, next != nullptr, n);
+        if (t) {
+            o.block = t >> 8;
+            o.schedule = t & 0xff;
+        }
+    }
     bool persistent = o.schedule == FW_SCHED_PERSISTENT;
     if (o.schedule == FW_SCHED_AUTO)
         persistent = (o.block == 0 || o.block == fw::kTile) && n > fw::kTile && !(next && n >= 16384);
@@ -200,6 +222,30 @@ fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
     return FW_OK;
 }
 
+// Wall-clock ticks of a dependency wait's bound (20 s; 0 for the test flag).
+fw_status wait_bound(bool test_timeout, uint64_t *ticks) {
+    hipError_t e;
+    int dev = 0, khz = 0;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess) return hip_fail(e, "wall clock rate");
+    if (khz <= 0) khz = 100000;
+    *ticks = test_timeout ? 0 : (uint64_t)khz * 1000ull * 20ull;
+    return FW_OK;
+}
+
+// Automatic team limit: the tuned table when it has an entry for this
+// (dtype, successors, largest tile count), else (measured on MI355X) one
+// workgroup per graph up to two tiles per side, and 2 nt workgroups above:
+// a round's critical path (phase 1, a band tile, a remaining tile) leaves
+// larger teams waiting while other graphs could run.
+int auto_team(fw::DType dt, bool next, int n_max) {
+    const int nt = (n_max + fw::kTile - 1) / fw::kTile;
+    const int tuned = tuned_team(dt, next, nt);
+    if (tuned > 0) return tuned;
+    return nt <= 2 ? 1 : 2 * nt;
+}
+
 fw_status solve_batched(fw::DType dt, void *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
                         int32_t batch, int32_t n_max, const fw_options *opt, void *stream) {
     g_err[0] = 0;
@@ -208,17 +254,22 @@ fw_status solve_batched(fw::DType dt, void *dist, int32_t *next, const int64_t *
     if (!dist || !d_offset || !d_n) return fail(FW_ERR_INVALID_ARG, "dist, d_offset and d_n must not be NULL");
     if (n_max < 1 || n_max > 65536)
         return fail(FW_ERR_INVALID_ARG, "n_max = %d (allowed: 1 .. 65536)", n_max);
-    fw_options o = {0, FW_SCHED_AUTO, 0, 0};
+    if (batch > 65535) return fail(FW_ERR_UNSUPPORTED, "batch = %d (at most 65535 graphs per call)", batch);
+    fw_options o = {0, FW_SCHED_AUTO, 0, 0, 0};
     if (opt) {
-        if (opt->flags & ~(FW_FLAG_EAGER_ARGMIN)) return fail(FW_ERR_INVALID_ARG, "flags = %d", opt->flags);
+        if (opt->flags & ~(FW_FLAG_EAGER_ARGMIN | FW_FLAG_TEST_TIMEOUT))
+            return fail(FW_ERR_INVALID_ARG, "flags = %d", opt->flags);
         if (opt->block != 0 && opt->block != fw::kTile)
             return fail(FW_ERR_UNSUPPORTED, "batched solves run block size %d only", fw::kTile);
+        if (opt->team < 0) return fail(FW_ERR_INVALID_ARG, "team = %d is negative", opt->team);
         o = *opt;
     }
+    const int team = o.team ? o.team : auto_team(dt, next != nullptr, n_max);
     fw::DeviceWork *work = nullptr;
     fw_status s = get_work(&work);
     if (s != FW_OK) return s;
-    s = grow_ints(&work->batch, &work->batch_ints, (int64_t)n_max + 2 + batch, "batch workspace");
+    s = grow_ints(&work->batch, &work->batch_ints, fw::batched_workspace_ints(batch, n_max, team),
+                  "batch workspace");
     if (s != FW_OK) return s;
     fw::BatchPlan b;
     b.dtype = dt;
@@ -230,11 +281,164 @@ fw_status solve_batched(fw::DType dt, void *dist, int32_t *next, const int64_t *
     b.n_max = n_max;
     b.validate = o.validate != 0;
     b.eager_argmin = (o.flags & FW_FLAG_EAGER_ARGMIN) != 0;
+    b.team_cap = team;
+    s = wait_bound((o.flags & FW_FLAG_TEST_TIMEOUT) != 0, &b.timeout_ticks);
+    if (s != FW_OK) return s;
     b.scratch = work->batch;
     b.err = work->err;
     b.stream = (hipStream_t)stream;
     hipError_t e = fw::launch_batched(b);
     if (e != hipSuccess) return hip_fail(e, "batched launch");
+    return FW_OK;
+}
+
+// ---- autotuners: time the candidates on the caller's own input (restored
+// from a scratch copy before every run) and record the fastest.
+struct TuneCtx {
+    hipStream_t st;
+    void *backup = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    ~TuneCtx() {
+        if (backup) (void)hipFree(backup);
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+fw_status device_error() {
+    fw::DeviceWork *w = nullptr;
+    fw_status s = get_work(&w);
+    if (s != FW_OK) return s;
+    int code = 0;
+    hipError_t e = hipMemcpy(&code, w->err, sizeof code, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(error word)");
+    if (code) {
+        (void)hipMemset(w->err, 0, sizeof code);
+        return fail(code == 2 ? FW_ERR_TIMEOUT : code == 1 ? FW_ERR_NEGATIVE : FW_ERR_INVALID_ARG,
+                    "device error %d while tuning", code);
+    }
+    return FW_OK;
+}
+
+// Runs `run` reps times after one warm-up, each after restoring `bytes` of
+// dist from the backup; returns the mean time of the run itself.
+template <typename F>
+fw_status time_runs(TuneCtx &c, void *dist, size_t bytes, int reps, F run, double *ms) {
+    hipError_t e;
+    double tot = 0;
+    for (int r = -1; r < reps; ++r) {
+        if ((e = hipMemcpyAsync(dist, c.backup, bytes, hipMemcpyDeviceToDevice, c.st)) != hipSuccess)
+            return hip_fail(e, "restore input");
+        if ((e = hipEventRecord(c.a, c.st)) != hipSuccess) return hip_fail(e, "event");
+        fw_status s = run();
+        if (s != FW_OK) return s;
+        if ((e = hipEventRecord(c.b, c.st)) != hipSuccess) return hip_fail(e, "event");
+        if ((e = hipEventSynchronize(c.b)) != hipSuccess) return hip_fail(e, "event sync");
+        float t = 0;
+        if ((e = hipEventElapsedTime(&t, c.a, c.b)) != hipSuccess) return hip_fail(e, "event time");
+        if (r >= 0) tot += t;
+    }
+    fw_status s = device_error();
+    if (s != FW_OK) return s;
+    *ms = tot / reps;
+    return FW_OK;
+}
+
+fw_status tune_begin(TuneCtx &c, void *dist, size_t bytes, void *stream) {
+    c.st = (hipStream_t)stream;
+    hipError_t e = hipMalloc(&c.backup, bytes ? bytes : 1);
+    if (e != hipSuccess) return hip_fail(e, "tuning backup");
+    if ((e = hipEventCreate(&c.a)) != hipSuccess || (e = hipEventCreate(&c.b)) != hipSuccess)
+        return hip_fail(e, "tuning events");
+    if ((e = hipMemcpyAsync(c.backup, dist, bytes, hipMemcpyDeviceToDevice, c.st)) != hipSuccess)
+        return hip_fail(e, "tuning backup copy");
+    return FW_OK;
+}
+
+fw_status tune_end(TuneCtx &c, void *dist, size_t bytes) {
+    hipError_t e = hipMemcpyAsync(dist, c.backup, bytes, hipMemcpyDeviceToDevice, c.st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.st);
+    if (e != hipSuccess) return hip_fail(e, "restore input");
+    return FW_OK;
+}
+
+fw_status tune_batched(fw::DType dt, void *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
+                       int32_t batch, int32_t n_max, int64_t elems, int32_t reps, int32_t *best_team,
+                       double *best_ms, void *stream) {
+    g_err[0] = 0;
+    if (batch < 0) return fail(FW_ERR_INVALID_ARG, "batch = %d is negative", batch);
+    if (batch == 0) return FW_OK;
+    if (!dist || !d_offset || !d_n) return fail(FW_ERR_INVALID_ARG, "dist, d_offset and d_n must not be NULL");
+    if (n_max < 1 || n_max > 65536) return fail(FW_ERR_INVALID_ARG, "n_max = %d (allowed: 1 .. 65536)", n_max);
+    if (elems < 0 || reps < 1) return fail(FW_ERR_INVALID_ARG, "elems = %lld, reps = %d", (long long)elems, reps);
+    const size_t bytes = (size_t)elems * 4;
+    TuneCtx c;
+    fw_status s = tune_begin(c, dist, bytes, stream);
+    if (s != FW_OK) return s;
+    // candidates: 1 (a workgroup per graph), then powers of two up to every
+    // tile of the largest graph's round
+    const int nt = (n_max + fw::kTile - 1) / fw::kTile;
+    const int most = nt * nt;
+    std::vector<int> cands;
+    for (int v = 1; v < most; v *= 2) cands.push_back(v);
+    cands.push_back(most);
+    int best = 1;
+    double best_t = 1e30;
+    for (int cand : cands) {
+        fw_options o = {0, FW_SCHED_AUTO, 0, 0, cand};
+        double t = 0;
+        s = time_runs(c, dist, bytes, reps,
+                      [&] { return solve_batched(dt, dist, next, d_offset, d_n, batch, n_max, &o, stream); }, &t);
+        if (s != FW_OK) return s;
+        if (t < best_t) {
+            best_t = t;
+            best = cand;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[tune_key(dt, next != nullptr, nt)] = best;
+    }
+    if ((s = tune_end(c, dist, bytes)) != FW_OK) return s;
+    if (best_team) *best_team = best;
+    if (best_ms) *best_ms = best_t;
+    return FW_OK;
+}
+
+fw_status tune_solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld, int32_t reps,
+                     int32_t *best_block, int32_t *best_schedule, double *best_ms, void *stream) {
+    g_err[0] = 0;
+    fw_status s = check_args(dist, n, ld, nullptr);
+    if (s != FW_OK) return s;
+    if (reps < 1) return fail(FW_ERR_INVALID_ARG, "reps = %d", reps);
+    if (n == 0) return FW_OK;
+    const size_t bytes = (size_t)((n - 1) * ld + n) * 4;
+    TuneCtx c;
+    if ((s = tune_begin(c, dist, bytes, stream)) != FW_OK) return s;
+    const int cands[][2] = {{32, FW_SCHED_THREE_LAUNCH}, {64, FW_SCHED_THREE_LAUNCH},
+                            {128, FW_SCHED_THREE_LAUNCH}, {128, FW_SCHED_PERSISTENT}};
+    int bb = 128, bsch = FW_SCHED_THREE_LAUNCH;
+    double best_t = 1e30;
+    for (auto &cd : cands) {
+        if (cd[1] == FW_SCHED_PERSISTENT && n <= fw::kTile) continue;
+        fw_options o = {cd[0], cd[1], 0, 0, 0};
+        double t = 0;
+        s = time_runs(c, dist, bytes, reps, [&] { return solve(dt, dist, next, n, ld, &o, stream); }, &t);
+        if (s != FW_OK) return s;
+        if (t < best_t) {
+            best_t = t;
+            bb = cd[0];
+            bsch = cd[1];
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned_solve[solve_key(dt, next != nullptr, n)] = (bb << 8) | bsch;
+    }
+    if ((s = tune_end(c, dist, bytes)) != FW_OK) return s;
+    if (best_block) *best_block = bb;
+    if (best_schedule) *best_schedule = bsch;
+    if (best_ms) *best_ms = best_t;
     return FW_OK;
 }
 
@@ -285,6 +489,30 @@ fw_status backward(const float *G, const int32_t *next, float *dW, int64_t n, in
 }  // namespace
 
 extern "C" {
+
+fw_status fw_tune_batched_i32(int32_t *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
+                              int32_t batch, int32_t n_max, int64_t elems, int32_t reps, int32_t *best_team,
+                              double *best_ms, void *stream) {
+    return tune_batched(fw::DType::I32, dist, next, d_offset, d_n, batch, n_max, elems, reps, best_team, best_ms,
+                        stream);
+}
+
+fw_status fw_tune_batched_f32(float *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
+                              int32_t batch, int32_t n_max, int64_t elems, int32_t reps, int32_t *best_team,
+                              double *best_ms, void *stream) {
+    return tune_batched(fw::DType::F32, dist, next, d_offset, d_n, batch, n_max, elems, reps, best_team, best_ms,
+                        stream);
+}
+
+fw_status fw_tune_solve_i32(int32_t *dist, int32_t *next, int64_t n, int64_t ld, int32_t reps, int32_t *best_block,
+                            int32_t *best_schedule, double *best_ms, void *stream) {
+    return tune_solve(fw::DType::I32, dist, next, n, ld, reps, best_block, best_schedule, best_ms, stream);
+}
+
+fw_status fw_tune_solve_f32(float *dist, int32_t *next, int64_t n, int64_t ld, int32_t reps, int32_t *best_block,
+                            int32_t *best_schedule, double *best_ms, void *stream) {
+    return tune_solve(fw::DType::F32, dist, next, n, ld, reps, best_block, best_schedule, best_ms, stream);
+}
 
 fw_status fw_backward_f32(const float *grad_dist, const int32_t *next, float *grad_w, int64_t n, int64_t ld,
                           void *stream) {

@@ -47,7 +47,9 @@ struct BatchPlan {
     const int32_t *nv;         // device: vertices of graph g
     int batch, n_max;
     bool validate, eager_argmin;
-    int *scratch;              // n_max + 2 + batch ints (order and counts)
+    int team_cap;              // 1: one workgroup per graph; else team schedule
+    uint64_t timeout_ticks;    // team schedule: wait bound
+    int *scratch;              // batched_workspace_ints(batch, n_max, team_cap) ints
     int *err;
     hipStream_t stream;
 };
@@ -80,5 +82,6 @@ hipError_t launch_phase3(const Plan &p, int K);
 hipError_t launch_persistent(const Plan &p);
 int64_t persistent_workspace_ints(int rounds, int nt);
 hipError_t launch_batched(const BatchPlan &b);
+int64_t batched_workspace_ints(int batch, int n_max, int team_cap);
 
 }  // namespace fw

@@ -838,16 +838,17 @@ template <typename U, int ARGMIN> union PersistSmem {
     Phase1Smem<U, kTile, ARGMIN != 0> p1;      // successors in LDS
 };
 
+// The whole solve of one graph by the workgroups that call it (every
+// workgroup of the persistent launch, or a team of the batched one).  Returns
+// false when the solve was aborted (a wait passed its deadline).
 template <typename U, int ARGMIN, bool VEC>
-__global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 1 ? 1 : 4) void persistent_kernel(
-        U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int R, int nt,
-        int *__restrict__ wsp, int *__restrict__ err, uint64_t timeout_ticks) {
+__device__ __forceinline__ bool persistent_solve(U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld,
+                                                 int R, int nt, const PersistWs &ws, int *__restrict__ err,
+                                                 uint64_t timeout_ticks, PersistSmem<U, ARGMIN> &sm, int &s_item,
+                                                 int &s_ok) {
     constexpr int NT = MinplusSmem<U, ARGMIN>::NT;
     constexpr bool NEXT = ARGMIN != 0;
     constexpr int BS = kTile;
-    __shared__ PersistSmem<U, ARGMIN> sm;
-    __shared__ int s_item, s_ok;
-    const PersistWs ws = persist_ws(wsp, R, nt);
     const int items = 1 + 2 * nt + nt * nt;
     const bool lead = threadIdx.x == 0;
 
@@ -937,7 +938,7 @@ __global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 1 ? 1 : 4) void 
                     wait_vmem();
                 }
                 __syncthreads();
-                if (!s_ok) return;
+                if (!s_ok) return false;
                 if (item > 2 * nt && work && s_ok == 2) ready3 = true;
             }
             // ---- the work
@@ -969,8 +970,19 @@ __global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 1 ? 1 : 4) void 
             release_agent();
             __hip_atomic_fetch_add(&ws.done[K], mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        if (ld_flag(ws.abort)) return;
+        if (ld_flag(ws.abort)) return false;
     }
+    return true;
+}
+
+template <typename U, int ARGMIN, bool VEC>
+__global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 1 ? 1 : 4) void persistent_kernel(
+        U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int R, int nt,
+        int *__restrict__ wsp, int *__restrict__ err, uint64_t timeout_ticks) {
+    __shared__ PersistSmem<U, ARGMIN> sm;
+    __shared__ int s_item, s_ok;
+    persistent_solve<U, ARGMIN, VEC>(D, NX, n, ld, R, nt, persist_ws(wsp, R, nt), err, timeout_ticks, sm, s_item,
+                                     s_ok);
 }
 
 // ------------------------------------------------------------- batched solve
@@ -987,14 +999,29 @@ template <typename U, int ARGMIN> union BatchSmem {
     Phase1Smem<U, kTile, false> p1;
 };
 
+// Workgroups that may share one graph in the team schedule: every tile of
+// a round at most, capped by the caller's limit; a one-tile graph is a single
+// phase-1 closure.
+__host__ __device__ __forceinline__ int team_size(int64_t n, int team_cap) {
+    const int64_t nt = (n + kTile - 1) / kTile;
+    if (nt <= 1) return 1;
+    const int64_t t = nt * nt;
+    return (int)(t < team_cap ? t : team_cap);
+}
+
 // Counting sort of graph indices by decreasing n (one workgroup).  cnt must
-// hold n_max + 2 ints of scratch.
+// hold n_max + 2 ints of scratch.  With cum != nullptr it also writes the
+// team schedule's ticket ranges: sorted graph s owns tickets
+// [cum[s], cum[s+1]), and resets the ticket counter.
 __global__ __launch_bounds__(1024) void batch_order_kernel(const int32_t *__restrict__ nv, int batch, int n_max,
                                                           int *__restrict__ cnt, int *__restrict__ perm,
-                                                          int *__restrict__ err) {
-    for (int v = threadIdx.x; v <= n_max + 1; v += blockDim.x) cnt[v] = 0;
+                                                          int *__restrict__ err, int team_cap,
+                                                          int *__restrict__ cum, int *__restrict__ ticket) {
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    for (int v = t; v <= n_max + 1; v += blockDim.x) cnt[v] = 0;
     __syncthreads();
-    for (int g = threadIdx.x; g < batch; g += blockDim.x) {
+    for (int g = t; g < batch; g += blockDim.x) {
         int m = nv[g];
         if (m < 0 || m > n_max) {
             atomicCAS(err, 0, 3);
@@ -1003,7 +1030,7 @@ __global__ __launch_bounds__(1024) void batch_order_kernel(const int32_t *__rest
         atomicAdd(&cnt[n_max - m], 1);            // bucket 0 = largest n
     }
     __syncthreads();
-    if (threadIdx.x == 0) {                       // exclusive prefix sum (n_max is small)
+    if (t == 0) {                                 // exclusive prefix sum (n_max is small)
         int acc = 0;
         for (int v = 0; v <= n_max; ++v) {
             const int c = cnt[v];
@@ -1012,10 +1039,114 @@ __global__ __launch_bounds__(1024) void batch_order_kernel(const int32_t *__rest
         }
     }
     __syncthreads();
-    for (int g = threadIdx.x; g < batch; g += blockDim.x) {
+    for (int g = t; g < batch; g += blockDim.x) {
         int m = nv[g];
         if (m < 0 || m > n_max) m = 0;
         perm[atomicAdd(&cnt[n_max - m], 1)] = g;
+    }
+    if (!cum) return;
+    __syncthreads();
+    // ticket ranges: each thread scans a contiguous run of sorted positions
+    const int per = (batch + 1023) / 1024;
+    const int lo = (int)imin64((int64_t)t * per, batch), hi = (int)imin64((int64_t)lo + per, batch);
+    int acc = 0;
+    for (int q = lo; q < hi; ++q) {
+        const int m = nv[perm[q]];
+        acc += (m < 0 || m > n_max) ? 0 : team_size(m, team_cap);
+    }
+    part[t] = acc;
+    __syncthreads();
+    if (t == 0) {
+        int run = 0;
+        for (int v = 0; v < 1024; ++v) {
+            const int c = part[v];
+            part[v] = run;
+            run += c;
+        }
+        cum[batch] = run;
+        *ticket = 0;
+    }
+    __syncthreads();
+    acc = part[t];
+    for (int q = lo; q < hi; ++q) {
+        cum[q] = acc;
+        const int m = nv[perm[q]];
+        acc += (m < 0 || m > n_max) ? 0 : team_size(m, team_cap);
+    }
+}
+
+// Input normalisation of every graph of a batch (as init_kernel);
+// grid.y = graph.
+template <typename U>
+__global__ __launch_bounds__(256) void batch_init_kernel(U *__restrict__ D, int32_t *__restrict__ NX,
+                                                         const int64_t *__restrict__ off,
+                                                         const int32_t *__restrict__ nv, int n_max, int validate,
+                                                         int *__restrict__ err) {
+    const int g = blockIdx.y;
+    const int64_t n = nv[g];
+    if (n <= 0 || n > n_max) return;
+    U *Dg = D + off[g];
+    int32_t *NXg = NX ? NX + off[g] : nullptr;
+    bool any_bad = false;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n * n; q += (int64_t)gridDim.x * 256) {
+        const int64_t i = q / n, j = q % n;
+        bool bad;
+        const U w = norm_weight(Dg[q], i == j, bad);
+        any_bad |= bad;
+        Dg[q] = w;
+        if (NXg) NXg[q] = (i == j) ? (int32_t)i : (w < Arith<U>::inf() ? (int32_t)j : -1);
+    }
+    if (validate && any_bad) atomicCAS(err, 0, 1);
+}
+
+// Team schedule: a resident grid; each workgroup takes a ticket, which names
+// a graph (largest first) and makes it one member of that graph's team; the
+// team runs the persistent schedule of that graph with the graph's own flag
+// workspace, then each member takes another ticket.  Teams only wait on
+// items of their own graph that running members have taken, so the launch
+// needs no co-resident grid.  A one-tile graph is one phase-1 closure.
+template <typename U, int ARGMIN>
+__global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 1 ? 1 : 4) void batched_team_kernel(
+        U *__restrict__ D, int32_t *__restrict__ NX, const int64_t *__restrict__ off,
+        const int32_t *__restrict__ nv, const int *__restrict__ perm, const int *__restrict__ cum, int batch,
+        int n_max, int *__restrict__ ticket, int *__restrict__ wsbase, int64_t ws_stride, int *__restrict__ err,
+        uint64_t timeout_ticks) {
+    constexpr int NT = MinplusSmem<U, ARGMIN>::NT;
+    constexpr bool NEXT = ARGMIN != 0;
+    __shared__ PersistSmem<U, ARGMIN> sm;
+    __shared__ int s_item, s_ok, s_graph;
+    for (;;) {
+        __syncthreads();                           // s_graph of the previous graph is consumed
+        if (threadIdx.x == 0) {
+            const int tk = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            int sg = -1;
+            if (tk < cum[batch]) {                 // largest s with cum[s] <= tk
+                int lo = 0, hi = batch;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (cum[mid] <= tk) lo = mid;
+                    else hi = mid;
+                }
+                sg = lo;
+            }
+            s_graph = sg;
+        }
+        __syncthreads();
+        const int sg = s_graph;
+        if (sg < 0) return;
+        const int g = perm[sg];
+        const int64_t n = nv[g];
+        if (n <= 0 || n > n_max) continue;
+        U *Dg = D + off[g];
+        int32_t *NXg = NEXT ? NX + off[g] : nullptr;
+        const int nt = (int)((n + kTile - 1) / kTile);
+        if (nt == 1) {
+            phase1_block<U, NEXT, kTile, NT, NEXT>(Dg, NXg, n, n, 0, sm.p1);
+            continue;
+        }
+        const PersistWs ws = persist_ws(wsbase + (int64_t)sg * ws_stride, nt, nt);
+        if (!persistent_solve<U, ARGMIN, false>(Dg, NXg, n, n, nt, nt, ws, err, timeout_ticks, sm, s_item, s_ok))
+            return;
     }
 }
 
@@ -1143,15 +1274,65 @@ hipError_t persistent_dispatch(const Plan &p) {
     return p.vec ? persistent_t<U, 2, true>(p) : persistent_t<U, 2, false>(p);
 }
 
+// Batched scratch (ints): cnt[n_max + 2] | perm[batch] | cum[batch + 1] |
+// ticket, padded to 64 | team flag workspaces, ws_stride per sorted graph.
+struct BatchLayout {
+    int64_t cnt, perm, cum, ticket, ws, total, ws_stride;
+};
+BatchLayout batch_layout(int batch, int n_max, bool team) {
+    BatchLayout L;
+    L.cnt = 0;
+    L.perm = L.cnt + n_max + 2;
+    L.cum = L.perm + batch;
+    L.ticket = L.cum + batch + 1;
+    L.ws = ((L.ticket + 1 + 63) / 64) * 64;
+    const int nt = (n_max + kTile - 1) / kTile;
+    L.ws_stride = team && nt > 1 ? ((persist_ws_ints(nt, nt) + 15) / 16) * 16 : 0;
+    L.total = L.ws + (int64_t)batch * L.ws_stride;
+    return L;
+}
+
 template <typename U, int ARGMIN>
 hipError_t batched_t(const BatchPlan &b) {
     constexpr int NT = (ARGMIN == 2) ? 512 : 256;
-    hipLaunchKernelGGL(batch_order_kernel, dim3(1), dim3(1024), 0, b.stream, b.nv, b.batch, b.n_max, b.scratch,
-                       b.scratch + b.n_max + 2, b.err);
+    const bool team = b.team_cap != 1;
+    const BatchLayout L = batch_layout(b.batch, b.n_max, team);
+    int *sc = b.scratch;
+    hipLaunchKernelGGL(batch_order_kernel, dim3(1), dim3(1024), 0, b.stream, b.nv, b.batch, b.n_max, sc + L.cnt,
+                       sc + L.perm, b.err, b.team_cap, team ? sc + L.cum : nullptr, sc + L.ticket);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((batched_kernel<U, ARGMIN>), dim3((unsigned)b.batch), dim3(NT), 0, b.stream, (U *)b.dist,
-                       b.next, b.off, b.nv, b.scratch + b.n_max + 2, b.n_max, b.validate ? 1 : 0, b.err);
+    if (!team) {
+        hipLaunchKernelGGL((batched_kernel<U, ARGMIN>), dim3((unsigned)b.batch), dim3(NT), 0, b.stream,
+                           (U *)b.dist, b.next, b.off, b.nv, sc + L.perm, b.n_max, b.validate ? 1 : 0, b.err);
+        return hipGetLastError();
+    }
+    if (L.ws_stride > 0) {
+        const int64_t cnt = (int64_t)b.batch * L.ws_stride;
+        const unsigned zg = (unsigned)imin64((cnt + 255) / 256, 1024);
+        hipLaunchKernelGGL(zero_ints_kernel, dim3(zg), dim3(256), 0, b.stream, sc + L.ws, cnt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const int64_t nn = (int64_t)b.n_max * b.n_max;
+    const unsigned ix = (unsigned)imin64((nn + 255) / 256, 64);
+    hipLaunchKernelGGL(batch_init_kernel<U>, dim3(ix, (unsigned)b.batch), dim3(256), 0, b.stream, (U *)b.dist,
+                       b.next, b.off, b.nv, b.n_max, b.validate ? 1 : 0, b.err);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    auto kern = batched_team_kernel<U, ARGMIN>;
+    static int per_cu = -1;
+    int dev = 0, cus = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if (per_cu < 0) {
+        int nb = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(kern), NT, 0);
+        if (e != hipSuccess) return e;
+        per_cu = nb > 0 ? nb : 1;
+    }
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    const int64_t tickets = (int64_t)b.batch * team_size(b.n_max, b.team_cap);
+    const int grid = (int)imin64((int64_t)cus * per_cu, tickets);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), 0, b.stream, (U *)b.dist, b.next, b.off, b.nv, sc + L.perm,
+                       sc + L.cum, b.batch, b.n_max, sc + L.ticket, sc + L.ws, L.ws_stride, b.err, b.timeout_ticks);
     return hipGetLastError();
 }
 
@@ -1162,6 +1343,10 @@ hipError_t batched_dispatch(const BatchPlan &b) {
 }
 
 }  // namespace
+
+int64_t batched_workspace_ints(int batch, int n_max, int team_cap) {
+    return batch_layout(batch, n_max, team_cap != 1).total;
+}
 
 hipError_t launch_batched(const BatchPlan &b) {
     return b.dtype == DType::I32 ? batched_dispatch<uint32_t>(b) : batched_dispatch<float>(b);

@@ -92,3 +92,24 @@ def test_backward_invalid_arguments_rejected_on_host():
     assert "4096" in fw.last_error()
     assert g(FAKE, FAKE, FAKE, FAKE, FAKE, 70000, 16, None) == fw.FW_ERR_UNSUPPORTED
     assert g(None, None, None, None, None, 0, 16, None) == fw.FW_OK
+
+
+def test_tuners_reject_bad_arguments_on_host():
+    i32, dbl = ctypes.c_int32(), ctypes.c_double()
+    for fn in (fw.lib.fw_tune_batched_i32, fw.lib.fw_tune_batched_f32):
+        assert fn(FAKE, None, FAKE, FAKE, -1, 16, 10, 1, ctypes.byref(i32), ctypes.byref(dbl), None) == fw.FW_ERR_INVALID_ARG
+        assert fn(None, None, FAKE, FAKE, 4, 16, 10, 1, ctypes.byref(i32), ctypes.byref(dbl), None) == fw.FW_ERR_INVALID_ARG
+        assert fn(FAKE, None, FAKE, FAKE, 4, 0, 10, 1, ctypes.byref(i32), ctypes.byref(dbl), None) == fw.FW_ERR_INVALID_ARG
+        assert fn(FAKE, None, FAKE, FAKE, 4, 16, -1, 1, ctypes.byref(i32), ctypes.byref(dbl), None) == fw.FW_ERR_INVALID_ARG
+        assert fn(FAKE, None, FAKE, FAKE, 4, 16, 10, 0, ctypes.byref(i32), ctypes.byref(dbl), None) == fw.FW_ERR_INVALID_ARG
+        assert fn(None, None, None, None, 0, 16, 0, 1, None, None, None) == fw.FW_OK
+    for fn in (fw.lib.fw_tune_solve_i32, fw.lib.fw_tune_solve_f32):
+        assert fn(FAKE, None, -1, 4, 1, None, None, None, None) == fw.FW_ERR_INVALID_ARG
+        assert fn(FAKE, None, 8, 7, 1, None, None, None, None) == fw.FW_ERR_INVALID_ARG
+        assert fn(FAKE, None, 8, 8, 0, None, None, None, None) == fw.FW_ERR_INVALID_ARG
+        assert fn(None, None, 0, 0, 1, None, None, None, None) == fw.FW_OK
+
+
+def test_batched_rejects_negative_team():
+    opt = B.fw_options(0, 0, 0, 0, -2)
+    assert fw.lib.fw_solve_batched_f32(FAKE, None, FAKE, FAKE, 4, 16, ctypes.byref(opt), None) == fw.FW_ERR_INVALID_ARG
