@@ -13,7 +13,13 @@ Prints one JSON line.  Besides the driver's fields it carries
   roofline     : the phase-3 (min-plus) kernel, timed live with HIP events on
                  the solver's stream, against the MI355X VALU lane-op peak;
   cpu_baseline : the CPU oracle (plain triple loop) timed on this host on a
-                 bounded sample of the same recipe.
+                 bounded sample of the same recipe;
+  batched      : 4096 graphs, n ~ U{16..256}, edge prob 0.3, float32
+                 U[0.1,10): one captured HIP graph (input restore + batched
+                 solve) per step, beside the same graphs solved one call each;
+  fwdbwd       : 64 complete graphs, n ~ U{64..1024}, float32 U[0.5,1.5),
+                 N(0,1) upstream: autotuned batched forward, batched gradient
+                 pass, beside per-graph forward solves.
 """
 from __future__ import annotations
 
@@ -93,6 +99,125 @@ def cpu_baseline(args):
             "seconds": dt}
 
 
+def _pack(sizes, gen):
+    import numpy as np
+    offs = np.concatenate([[0], np.cumsum([int(n) * int(n) for n in sizes])[:-1]]).astype(np.int64)
+    arena = np.concatenate([gen(int(n), g).reshape(-1) for g, n in enumerate(sizes)])
+    return offs, arena
+
+
+def _time_graph(torch, graph, stream, reps):
+    """Mean ms of `reps` replays of a captured HIP graph (events on `stream`)."""
+    graph.replay()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        graph.replay()
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def _per_graph_loop(torch, fw, Ws, next_hop=True):
+    """Plain per-graph method: one restore + fw_solve call per graph."""
+    Ds = [torch.empty_like(w) for w in Ws]
+    Ns = [torch.empty(w.shape, dtype=torch.int32, device=w.device) for w in Ws] if next_hop else [None] * len(Ws)
+    for d, w, nx in zip(Ds, Ws, Ns):                   # warm-up: every size's workspace exists
+        d.copy_(w)
+        fw.solve_(d, nx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d, w, nx in zip(Ds, Ws, Ns):
+        d.copy_(w)
+        fw.solve_(d, nx)
+    torch.cuda.synchronize()
+    fw.check()
+    return (time.perf_counter() - t0) * 1e3
+
+
+def bench_batched(torch, fw, synth, reps):
+    import numpy as np
+    sizes = [int(x) for x in synth.batch_sizes()]
+    offs, arena = _pack(sizes, lambda n, g: synth.batch_graph_f32(n, g))
+    relax = float(sum(n ** 3 for n in sizes))
+    W0 = torch.from_numpy(arena).cuda()
+    D = torch.empty_like(W0)
+    NX = torch.empty(W0.numel(), dtype=torch.int32, device="cuda")
+    off = torch.from_numpy(offs).cuda()
+    sz = torch.from_numpy(np.asarray(sizes, np.int32)).cuda()
+    D.copy_(W0)
+    team, tune_ms = fw.tune_batched_(D, NX, off, sz, 256, reps=2)
+    D.copy_(W0)
+    fw.solve_batched_(D, NX, off, sz, 256)
+    torch.cuda.synchronize()
+    fw.check()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        D.copy_(W0)
+        fw.solve_batched_(D, NX, off, sz, 256)
+    ms = _time_graph(torch, g, torch.cuda.current_stream(), reps)
+    fw.check()
+    log(f"batched: {ms:.3f} ms per captured step (team {team})")
+    Ws = [torch.from_numpy(synth.batch_graph_f32(n, i)).cuda() for i, n in enumerate(sizes)]
+    loop_ms = _per_graph_loop(torch, fw, Ws)
+    log(f"batched: per-graph loop {loop_ms:.1f} ms")
+    return {"workload": "4096 directed graphs, n ~ U{16..256}, edge prob 0.3, float32 U[0.1,10), dist + next",
+            "graphs": len(sizes), "relaxations": relax, "ms_per_step": ms, "value": relax / (ms / 1e3),
+            "unit": "relaxations/s", "team": team, "step": "one HIP graph replay: input restore + fw_solve_batched",
+            "per_graph_ms": loop_ms, "per_graph_value": relax / (loop_ms / 1e3),
+            "per_graph_step": "4096 x (restore + fw_solve_ex) calls from Python, one stream",
+            "speedup_vs_per_graph": loop_ms / ms}
+
+
+def bench_fwdbwd(torch, fw, synth, reps):
+    import numpy as np
+    sizes = [int(x) for x in synth.fwdbwd_sizes()]
+    n_max = max(sizes)
+    offs, arena = _pack(sizes, lambda n, g: synth.fwdbwd_graph_f32(n, g))
+    _, ups = _pack(sizes, lambda n, g: synth.fwdbwd_upstream(n, g))
+    relax = float(sum(n ** 3 for n in sizes))
+    W0 = torch.from_numpy(arena).cuda()
+    G = torch.from_numpy(ups).cuda()
+    D = torch.empty_like(W0)
+    NX = torch.empty(W0.numel(), dtype=torch.int32, device="cuda")
+    dW = torch.empty_like(W0)
+    off = torch.from_numpy(offs).cuda()
+    sz = torch.from_numpy(np.asarray(sizes, np.int32)).cuda()
+    D.copy_(W0)
+    team, _ = fw.tune_batched_(D, NX, off, sz, n_max, reps=2)
+    D.copy_(W0)
+    fw.solve_batched_(D, NX, off, sz, n_max)
+    fw.backward_batched_(G, NX, dW, off, sz, n_max)
+    torch.cuda.synchronize()
+    fw.check()
+    gf = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gf):
+        D.copy_(W0)
+        fw.solve_batched_(D, NX, off, sz, n_max)
+    gb = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gb):
+        fw.backward_batched_(G, NX, dW, off, sz, n_max)
+    st = torch.cuda.current_stream()
+    fwd_ms = _time_graph(torch, gf, st, reps)
+    bwd_ms = _time_graph(torch, gb, st, reps)
+    fw.check()
+    log(f"fwdbwd: forward {fwd_ms:.3f} ms (team {team}), backward {bwd_ms:.3f} ms")
+    Ws = [torch.from_numpy(synth.fwdbwd_graph_f32(n, i)).cuda() for i, n in enumerate(sizes)]
+    loop_ms = _per_graph_loop(torch, fw, Ws)
+    elems = float(sum(n * n for n in sizes))
+    return {"workload": "64 complete directed graphs, n ~ U{64..1024}, float32 U[0.5,1.5), upstream N(0,1)",
+            "graphs": len(sizes), "relaxations": relax, "team": team,
+            "forward_ms": fwd_ms, "backward_ms": bwd_ms, "total_ms": fwd_ms + bwd_ms,
+            "forward_value": relax / (fwd_ms / 1e3), "unit": "relaxations/s",
+            "fwdbwd_value": relax / ((fwd_ms + bwd_ms) / 1e3),
+            "backward_GBps": 16.0 * elems / (bwd_ms / 1e3) / 1e9,
+            "backward_bytes_per_element": 16,
+            "per_graph_forward_ms": loop_ms, "per_graph_forward_value": relax / (loop_ms / 1e3),
+            "speedup_forward_vs_per_graph": loop_ms / fwd_ms}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,8 +232,10 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--no-next", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=4096)
+    ap.add_argument("--cpu-n", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and forward+backward lines")
+    ap.add_argument("--extra-reps", type=int, default=5)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -174,6 +301,14 @@ def main():
                 "ops_per_relaxation": OPS_PER_RELAX}
     phase_ms = {k: (v[0] / args.steps) for k, v in ph.items() if v[1]}
 
+    has_next = NX is not None
+    del D, NX, Wd
+    torch.cuda.empty_cache()
+    batched = fwdbwd = None
+    if not args.no_extras:
+        batched = bench_batched(torch, fw, synth, args.extra_reps)
+        fwdbwd = bench_fwdbwd(torch, fw, synth, args.extra_reps)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args)
@@ -181,7 +316,7 @@ def main():
     wl = (f"blocked FW, one directed graph n={n}, edge prob {args.p}, "
           f"{'int32' if args.dtype == 'i32' else 'float32'} weights U[{args.lo:g},{args.hi:g}]"
           f"{', INF 2^30' if args.dtype == 'i32' else ''}, "
-          f"{'dist + int32 next-hop' if NX is not None else 'dist only'}")
+          f"{'dist + int32 next-hop' if has_next else 'dist only'}")
     out = {
         "metric": "n^3 relaxations/s, blocked FW n=32768; batched + fwd/bwd vs plain, 1 GPU",
         "value": value, "unit": "relaxations/s", "n_gpus": 1, "steps": args.steps,
@@ -191,10 +326,12 @@ def main():
         "data": "synthetic (seeded counter-based generator)",
         "config": {"workload": wl, "n": n, "block": bs,
                    "schedule": {0: "auto", 1: "three-launch", 2: "persistent"}[args.schedule],
-                   "next_hop": NX is not None, "seed": args.seed},
+                   "next_hop": has_next, "seed": args.seed},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phase_ms_per_step": phase_ms,
+        "batched": batched,
+        "fwdbwd": fwdbwd,
     }
     print(json.dumps(out), flush=True)
 
