@@ -37,8 +37,10 @@ sys.path.insert(0, ROOT)
 VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # fewest VALU lane-ops one min-plus relaxation needs on CDNA4: one 32-bit add
 # plus half of a three-input min (v_min3 folds two candidates into the running
-# minimum)
-OPS_PER_RELAX = 1.5
+# minimum); float64 has no three-input min: one v_add_f64 and one v_min_f64,
+# each at the full lane rate (MI355X: 78.6 TFLOP/s FP64 vector = 2 x 39.3 T
+# lane-FMAs/s)
+OPS_PER_RELAX = {"i32": 1.5, "f32": 1.5, "f64": 2.0}
 
 
 def log(msg):
@@ -85,9 +87,12 @@ def cpu_baseline(args):
     if args.dtype == "i32":
         W = synth.graph_i32(m, args.seed, args.p, args.lo, args.hi)
         fn = oracle.fw_i32
-    else:
+    elif args.dtype == "f32":
         W = synth.graph_f32(m, args.seed, args.p, args.lo, args.hi)
         fn = oracle.fw_f32
+    else:
+        W = synth.graph_f32(m, args.seed, args.p, args.lo, args.hi).astype("float64")
+        fn = oracle.fw_f64
     log(f"cpu baseline: oracle on n={m}, {threads} threads")
     t0 = time.perf_counter()
     fn(W, next_hop=not args.no_next, nthreads=threads)
@@ -224,7 +229,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=32768)
-    ap.add_argument("--dtype", choices=["i32", "f32"], default="i32")
+    ap.add_argument("--dtype", choices=["i32", "f32", "f64"], default="i32")
     ap.add_argument("--p", type=float, default=0.8)
     ap.add_argument("--lo", type=float, default=1)
     ap.add_argument("--hi", type=float, default=10000)
@@ -253,8 +258,10 @@ def main():
     log(f"generating n={n} {args.dtype} graph (p={args.p}, U[{args.lo},{args.hi}], seed {args.seed})")
     if args.dtype == "i32":
         W = synth.graph_i32(n, args.seed, args.p, int(args.lo), int(args.hi))
-    else:
+    elif args.dtype == "f32":
         W = synth.graph_f32(n, args.seed, args.p, args.lo, args.hi)
+    else:
+        W = synth.graph_f32(n, args.seed, args.p, args.lo, args.hi).astype(np.float64)
     dev = torch.device("cuda:0")
     Wd = torch.from_numpy(W).to(dev)
     del W
@@ -293,12 +300,13 @@ def main():
     relax_per_solve = phase3_relaxations(n, bs) if kind == "phase3" else n ** 3
     relax_per_launch = relax_per_solve / (k_launches / args.steps)
     avg_s = k_ms / k_launches / 1e3
-    achieved = OPS_PER_RELAX * relax_per_launch / avg_s
+    ops = OPS_PER_RELAX[args.dtype]
+    achieved = ops * relax_per_launch / avg_s
     traffic = load_traffic(f"{args.dtype}_n{n}_bs{bs}_{'next' if NX is not None else 'dist'}")
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
                 "unit": "Top/s", "frac": achieved / VALU_PEAK_LANE_OPS, "traffic": traffic,
                 "kernel": kind, "avg_launch_ms": avg_s * 1e3, "launches_per_step": k_launches / args.steps,
-                "ops_per_relaxation": OPS_PER_RELAX}
+                "ops_per_relaxation": ops}
     phase_ms = {k: (v[0] / args.steps) for k, v in ph.items() if v[1]}
 
     has_next = NX is not None
@@ -314,7 +322,7 @@ def main():
         cpu = cpu_baseline(args)
 
     wl = (f"blocked FW, one directed graph n={n}, edge prob {args.p}, "
-          f"{'int32' if args.dtype == 'i32' else 'float32'} weights U[{args.lo:g},{args.hi:g}]"
+          f"{ {'i32': 'int32', 'f32': 'float32', 'f64': 'float64'}[args.dtype]} weights U[{args.lo:g},{args.hi:g}]"
           f"{', INF 2^30' if args.dtype == 'i32' else ''}, "
           f"{'dist + int32 next-hop' if has_next else 'dist only'}")
     out = {
@@ -322,7 +330,7 @@ def main():
         "value": value, "unit": "relaxations/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "int32" if args.dtype == "i32" else "f32",
+        "dtype": {"i32": "int32", "f32": "f32", "f64": "f64"}[args.dtype],
         "data": "synthetic (seeded counter-based generator)",
         "config": {"workload": wl, "n": n, "block": bs,
                    "schedule": {0: "auto", 1: "three-launch", 2: "persistent"}[args.schedule],

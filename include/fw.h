@@ -20,8 +20,10 @@
  *    distance and next-hop matrices share `ld`.
  *  - int32 weights: an entry >= FW_INF_I32 (2^30) means "no edge" and is
  *    rewritten to FW_INF_I32.  Finite shortest-path lengths must stay below
- *    2^30.  float32 weights: +INFINITY means "no edge".  Weights must be
- *    >= 0 (no NaN); the diagonal is forced to 0 (self-loops are ignored).
+ *    2^30.  float32 / float64 weights: +INFINITY means "no edge".  Weights
+ *    must be >= 0 (no NaN); the diagonal is forced to 0 (self-loops are
+ *    ignored).  The float64 entry points (_f64) compute every sum in double
+ *    precision (the paper measures float and double, Section 4).
  *  - next (may be NULL: distances only) receives the successor matrix:
  *    next[i][j] is the vertex after i on the chosen shortest path from i to
  *    j, next[i][i] = i, next[i][j] = -1 when j is unreachable.  (The paper's
@@ -103,6 +105,9 @@ fw_status fw_solve_ex_i32(int32_t *dist, int32_t *next, int64_t n, int64_t ld,
                           const fw_options *opt, void *stream);
 fw_status fw_solve_ex_f32(float *dist, int32_t *next, int64_t n, int64_t ld,
                           const fw_options *opt, void *stream);
+fw_status fw_solve_f64(double *dist, int32_t *next, int64_t n, int64_t ld, void *stream);
+fw_status fw_solve_ex_f64(double *dist, int32_t *next, int64_t n, int64_t ld,
+                          const fw_options *opt, void *stream);
 
 /* Batched solve: `batch` independent graphs in one launch (the batched
  * configuration of the measurements; the paper solves one matrix at a time).
@@ -131,6 +136,8 @@ fw_status fw_solve_batched_i32(int32_t *dist, int32_t *next, const int64_t *d_of
                                int32_t batch, int32_t n_max, const fw_options *opt, void *stream);
 fw_status fw_solve_batched_f32(float *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
                                int32_t batch, int32_t n_max, const fw_options *opt, void *stream);
+fw_status fw_solve_batched_f64(double *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
+                               int32_t batch, int32_t n_max, const fw_options *opt, void *stream);
 
 /* Autotuners.  Each times its candidate configurations on the caller's own
  * input -- dist is copied to a scratch buffer first and restored before every
@@ -150,6 +157,8 @@ fw_status fw_tune_solve_i32(int32_t *dist, int32_t *next, int64_t n, int64_t ld,
                             int32_t *best_schedule, double *best_ms, void *stream);
 fw_status fw_tune_solve_f32(float *dist, int32_t *next, int64_t n, int64_t ld, int32_t reps, int32_t *best_block,
                             int32_t *best_schedule, double *best_ms, void *stream);
+fw_status fw_tune_solve_f64(double *dist, int32_t *next, int64_t n, int64_t ld, int32_t reps, int32_t *best_block,
+                            int32_t *best_schedule, double *best_ms, void *stream);
 
 /* fw_tune_batched_*: candidates team = 1, 2, 4, ... up to nt^2 (nt = tiles
  * per side of an n_max graph); the table key is (dtype, next != NULL, nt).
@@ -160,6 +169,9 @@ fw_status fw_tune_batched_i32(int32_t *dist, int32_t *next, const int64_t *d_off
                               int32_t batch, int32_t n_max, int64_t elems, int32_t reps, int32_t *best_team,
                               double *best_ms, void *stream);
 fw_status fw_tune_batched_f32(float *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
+                              int32_t batch, int32_t n_max, int64_t elems, int32_t reps, int32_t *best_team,
+                              double *best_ms, void *stream);
+fw_status fw_tune_batched_f64(double *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
                               int32_t batch, int32_t n_max, int64_t elems, int32_t reps, int32_t *best_team,
                               double *best_ms, void *stream);
 

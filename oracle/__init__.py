@@ -50,6 +50,8 @@ def load_library(path: str = _SO):
     lib.validate_walk_i32.restype = i64
     lib.validate_walk_f32.argtypes = [vp, i64, vp, vp, i64, i64, vp, i64, dbl, vp]
     lib.validate_walk_f32.restype = i64
+    lib.validate_walk_f64.argtypes = [vp, i64, vp, vp, i64, i64, vp, i64, dbl, vp]
+    lib.validate_walk_f64.restype = i64
     lib.oracle_grad_f64.argtypes = [vp, i64, vp, i64, i64, vp, i64]
     lib.oracle_grad_f64.restype = i64
     return lib
@@ -148,6 +150,12 @@ def validate_walk(W, D, NX, rows=None, rtol: float = 1e-5):
         D = np.ascontiguousarray(D, np.int32)
         bad = _L().validate_walk_i32(W.ctypes.data, W.shape[1], D.ctypes.data, NX.ctypes.data,
                                      D.shape[1], n, rows.ctypes.data, len(rows), first.ctypes.data)
+    elif D.dtype == np.float64:
+        W = np.ascontiguousarray(W, np.float64)
+        D = np.ascontiguousarray(D, np.float64)
+        bad = _L().validate_walk_f64(W.ctypes.data, W.shape[1], D.ctypes.data, NX.ctypes.data,
+                                     D.shape[1], n, rows.ctypes.data, len(rows), rtol,
+                                     first.ctypes.data)
     else:
         W = np.ascontiguousarray(W, np.float32)
         D = np.ascontiguousarray(D, np.float32)

@@ -121,3 +121,56 @@ int64_t validate_walk_f32(const float *W, int64_t ldw, const float *D,
     }
     return bad;
 }
+
+/* float64 distances: the same checks with the walk summed in float64 and
+ * compared within rtol. */
+int64_t validate_walk_f64(const double *W, int64_t ldw, const double *D,
+                          const int32_t *NX, int64_t ld, int64_t n,
+                          const int64_t *rows, int64_t nrows, double rtol,
+                          int64_t *first_bad) {
+    int64_t bad = 0;
+    first_bad[0] = first_bad[1] = -1;
+    first_bad[2] = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+:bad)
+    for (int64_t t = 0; t < nrows; ++t) {
+        const int64_t i = rows[t];
+        for (int64_t j = 0; j < n; ++j) {
+            const double d = D[i * ld + j];
+            const int32_t h0 = NX[i * ld + j];
+            int reason = 0;
+            if (i == j) {
+                if (d != 0.0 || h0 != (int32_t)i) reason = 1;
+            } else if (isinf(d) || h0 < 0) {
+                if (!(isinf(d) && d > 0 && h0 == -1)) reason = 2;
+            } else {
+                int64_t u = i, hops = 0;
+                double sum = 0.0;
+                while (u != j) {
+                    int32_t h = NX[u * ld + j];
+                    if (h < 0 || h >= n || h == u || hops >= n - 1) { reason = 3; break; }
+                    double w = W[u * ldw + h];
+                    if (isinf(w) || isnan(w) || w < 0.0) { reason = 3; break; }
+                    sum += w;
+                    u = h;
+                    ++hops;
+                }
+                if (!reason) {
+                    double scale = fabs(d) > fabs(sum) ? fabs(d) : fabs(sum);
+                    if (fabs(sum - d) > rtol * scale) reason = 4;
+                }
+            }
+            if (reason) {
+                ++bad;
+#pragma omp critical
+                {
+                    if (first_bad[0] < 0 || i < first_bad[0] || (i == first_bad[0] && j < first_bad[1])) {
+                        first_bad[0] = i;
+                        first_bad[1] = j;
+                        first_bad[2] = reason;
+                    }
+                }
+            }
+        }
+    }
+    return bad;
+}

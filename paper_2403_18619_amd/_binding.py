@@ -50,15 +50,15 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     opt_p = ctypes.POINTER(fw_options)
-    for name in ("fw_solve_i32", "fw_solve_f32"):
+    for name in ("fw_solve_i32", "fw_solve_f32", "fw_solve_f64"):
         f = getattr(lib, name)
         f.argtypes = [vp, vp, i64, i64, vp]
         f.restype = i32
-    for name in ("fw_solve_ex_i32", "fw_solve_ex_f32"):
+    for name in ("fw_solve_ex_i32", "fw_solve_ex_f32", "fw_solve_ex_f64"):
         f = getattr(lib, name)
         f.argtypes = [vp, vp, i64, i64, opt_p, vp]
         f.restype = i32
-    for name in ("fw_solve_batched_i32", "fw_solve_batched_f32"):
+    for name in ("fw_solve_batched_i32", "fw_solve_batched_f32", "fw_solve_batched_f64"):
         f = getattr(lib, name)
         f.argtypes = [vp, vp, vp, vp, i32, i32, opt_p, vp]
         f.restype = i32
@@ -66,11 +66,11 @@ def _load():
     lib.fw_backward_f32.restype = i32
     lib.fw_backward_batched_f32.argtypes = [vp, vp, vp, vp, vp, i32, i32, vp]
     lib.fw_backward_batched_f32.restype = i32
-    for name in ("fw_tune_batched_i32", "fw_tune_batched_f32"):
+    for name in ("fw_tune_batched_i32", "fw_tune_batched_f32", "fw_tune_batched_f64"):
         f = getattr(lib, name)
         f.argtypes = [vp, vp, vp, vp, i32, i32, i64, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double), vp]
         f.restype = i32
-    for name in ("fw_tune_solve_i32", "fw_tune_solve_f32"):
+    for name in ("fw_tune_solve_i32", "fw_tune_solve_f32", "fw_tune_solve_f64"):
         f = getattr(lib, name)
         f.argtypes = [vp, vp, i64, i64, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                       ctypes.POINTER(ctypes.c_double), vp]
@@ -137,12 +137,10 @@ def solve_(dist, next=None, *, block: int = 0, schedule: int = 0, validate: bool
     strides as ``dist``; receives the successor matrix."""
     import torch
     n, ld = _check_matrix(dist, "dist")
-    if dist.dtype == torch.int32:
-        fn = lib.fw_solve_ex_i32
-    elif dist.dtype == torch.float32:
-        fn = lib.fw_solve_ex_f32
-    else:
-        raise ValueError(f"dist dtype {dist.dtype} is not supported (int32 or float32)")
+    fn = {torch.int32: lib.fw_solve_ex_i32, torch.float32: lib.fw_solve_ex_f32,
+          torch.float64: lib.fw_solve_ex_f64}.get(dist.dtype)
+    if fn is None:
+        raise ValueError(f"dist dtype {dist.dtype} is not supported (int32, float32 or float64)")
     nptr = None
     if next is not None:
         if next.dtype != torch.int32 or next.shape != dist.shape or (n and next.stride() != dist.stride()):
@@ -185,11 +183,9 @@ def solve_batched_(dist, next, offsets, sizes, n_max: int, *, validate: bool = F
         raise ValueError("offsets must be int64 and sizes int32")
     if offsets.numel() != sizes.numel():
         raise ValueError("offsets and sizes must have one entry per graph")
-    if dist.dtype == torch.int32:
-        fn = lib.fw_solve_batched_i32
-    elif dist.dtype == torch.float32:
-        fn = lib.fw_solve_batched_f32
-    else:
+    fn = {torch.int32: lib.fw_solve_batched_i32, torch.float32: lib.fw_solve_batched_f32,
+          torch.float64: lib.fw_solve_batched_f64}.get(dist.dtype)
+    if fn is None:
         raise ValueError(f"dist dtype {dist.dtype} is not supported")
     if next is not None and (next.dtype != torch.int32 or next.numel() < dist.numel()):
         raise ValueError("next must be an int32 arena at least as large as dist")
@@ -251,7 +247,8 @@ def tune_solve_(dist, next=None, *, reps: int = 2, stream=None):
     schedule use the winner."""
     import torch
     n, ld = _check_matrix(dist, "dist")
-    fn = {torch.int32: lib.fw_tune_solve_i32, torch.float32: lib.fw_tune_solve_f32}.get(dist.dtype)
+    fn = {torch.int32: lib.fw_tune_solve_i32, torch.float32: lib.fw_tune_solve_f32,
+          torch.float64: lib.fw_tune_solve_f64}.get(dist.dtype)
     if fn is None:
         raise ValueError(f"dist dtype {dist.dtype} is not supported")
     if next is not None and (next.dtype != torch.int32 or next.shape != dist.shape or
@@ -270,7 +267,8 @@ def tune_batched_(dist, next, offsets, sizes, n_max: int, *, reps: int = 2, stre
     (fw_tune_batched_*).  dist keeps its input contents.  Returns (team,
     mean_ms); later batched solves with team=0 use the winner."""
     import torch
-    fn = {torch.int32: lib.fw_tune_batched_i32, torch.float32: lib.fw_tune_batched_f32}.get(dist.dtype)
+    fn = {torch.int32: lib.fw_tune_batched_i32, torch.float32: lib.fw_tune_batched_f32,
+          torch.float64: lib.fw_tune_batched_f64}.get(dist.dtype)
     if fn is None:
         raise ValueError(f"dist dtype {dist.dtype} is not supported")
     for t, name in ((dist, "dist"), (offsets, "offsets"), (sizes, "sizes")):

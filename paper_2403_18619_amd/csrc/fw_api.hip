@@ -47,13 +47,13 @@ fw_status get_work(fw::DeviceWork **out) {
     return FW_OK;
 }
 
-fw_status check_args(const void *dist, int64_t n, int64_t ld, const fw_options *opt) {
+fw_status check_args(const void *dist, int64_t n, int64_t ld, const fw_options *opt, int elem = 4) {
     if (n < 0) return fail(FW_ERR_INVALID_ARG, "n = %lld is negative", (long long)n);
     if (n >= (int64_t)INT32_MAX) return fail(FW_ERR_INVALID_ARG, "n = %lld does not fit the int32 successor matrix", (long long)n);
     if (n == 0) return FW_OK;
     if (!dist) return fail(FW_ERR_INVALID_ARG, "dist is NULL");
     if (ld < n) return fail(FW_ERR_INVALID_ARG, "ld = %lld < n = %lld", (long long)ld, (long long)n);
-    if (ld > INT64_MAX / 4 / n) return fail(FW_ERR_INVALID_ARG, "n * ld overflows");
+    if (ld > INT64_MAX / elem / n) return fail(FW_ERR_INVALID_ARG, "n * ld overflows");
     if (opt) {
         if (opt->block != 0 && opt->block != 32 && opt->block != 64 && opt->block != 128)
             return fail(FW_ERR_INVALID_ARG, "block = %d (allowed: 0, 32, 64, 128)", opt->block);
@@ -134,7 +134,7 @@ fw_status persistent_plan(fw::Plan &p, bool test_timeout) {
 std::mutex g_tune_mu;
 std::unordered_map<int64_t, int> g_tuned;
 int64_t tune_key(fw::DType dt, bool next, int nt) {
-    return ((int64_t)nt << 2) | ((int64_t)(dt == fw::DType::F32) << 1) | (int64_t)next;
+    return ((int64_t)nt << 3) | ((int64_t)dt << 1) | (int64_t)next;
 }
 int tuned_team(fw::DType dt, bool next, int nt) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -144,7 +144,7 @@ int tuned_team(fw::DType dt, bool next, int nt) {
 // single solves: (block << 8) | schedule per (dtype, successors, n)
 std::unordered_map<int64_t, int> g_tuned_solve;
 int64_t solve_key(fw::DType dt, bool next, int64_t n) {
-    return (n << 2) | ((int64_t)(dt == fw::DType::F32) << 1) | (int64_t)next;
+    return (n << 3) | ((int64_t)dt << 1) | (int64_t)next;
 }
 int tuned_solve(fw::DType dt, bool next, int64_t n) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -161,7 +161,7 @@ int auto_block(int64_t n) {
 fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
                 const fw_options *opt, void *stream) {
     g_err[0] = 0;
-    fw_status s = check_args(dist, n, ld, opt);
+    fw_status s = check_args(dist, n, ld, opt, fw::dtype_bytes(dt));
     if (s != FW_OK || n == 0) return s;
     fw_options o = {0, FW_SCHED_AUTO, 0, 0, 0};
     if (opt) o = *opt;
@@ -190,7 +190,7 @@ fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
     p.bs = persistent ? fw::kTile : (o.block ? o.block : auto_block(n));
     p.rounds = (int)((n + p.bs - 1) / p.bs);
     p.nt = (int)((n + fw::kTile - 1) / fw::kTile);
-    p.vec = (ld % 4 == 0) && ((uintptr_t)dist % 16 == 0);
+    p.vec = (ld % 4 == 0) && ((uintptr_t)dist % (4 * fw::dtype_bytes(dt)) == 0);   // 4-element vector accesses
     p.validate = o.validate != 0;
     p.eager_argmin = (o.flags & FW_FLAG_EAGER_ARGMIN) != 0;
     p.timeout_ticks = 0;
@@ -371,7 +371,7 @@ fw_status tune_batched(fw::DType dt, void *dist, int32_t *next, const int64_t *d
     if (!dist || !d_offset || !d_n) return fail(FW_ERR_INVALID_ARG, "dist, d_offset and d_n must not be NULL");
     if (n_max < 1 || n_max > 65536) return fail(FW_ERR_INVALID_ARG, "n_max = %d (allowed: 1 .. 65536)", n_max);
     if (elems < 0 || reps < 1) return fail(FW_ERR_INVALID_ARG, "elems = %lld, reps = %d", (long long)elems, reps);
-    const size_t bytes = (size_t)elems * 4;
+    const size_t bytes = (size_t)elems * fw::dtype_bytes(dt);
     TuneCtx c;
     fw_status s = tune_begin(c, dist, bytes, stream);
     if (s != FW_OK) return s;
@@ -408,11 +408,11 @@ fw_status tune_batched(fw::DType dt, void *dist, int32_t *next, const int64_t *d
 fw_status tune_solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld, int32_t reps,
                      int32_t *best_block, int32_t *best_schedule, double *best_ms, void *stream) {
     g_err[0] = 0;
-    fw_status s = check_args(dist, n, ld, nullptr);
+    fw_status s = check_args(dist, n, ld, nullptr, fw::dtype_bytes(dt));
     if (s != FW_OK) return s;
     if (reps < 1) return fail(FW_ERR_INVALID_ARG, "reps = %d", reps);
     if (n == 0) return FW_OK;
-    const size_t bytes = (size_t)((n - 1) * ld + n) * 4;
+    const size_t bytes = (size_t)((n - 1) * ld + n) * fw::dtype_bytes(dt);
     TuneCtx c;
     if ((s = tune_begin(c, dist, bytes, stream)) != FW_OK) return s;
     const int cands[][2] = {{32, FW_SCHED_THREE_LAUNCH}, {64, FW_SCHED_THREE_LAUNCH},
@@ -504,6 +504,18 @@ fw_status fw_tune_batched_f32(float *dist, int32_t *next, const int64_t *d_offse
                         stream);
 }
 
+fw_status fw_tune_batched_f64(double *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
+                              int32_t batch, int32_t n_max, int64_t elems, int32_t reps, int32_t *best_team,
+                              double *best_ms, void *stream) {
+    return tune_batched(fw::DType::F64, dist, next, d_offset, d_n, batch, n_max, elems, reps, best_team, best_ms,
+                        stream);
+}
+
+fw_status fw_tune_solve_f64(double *dist, int32_t *next, int64_t n, int64_t ld, int32_t reps, int32_t *best_block,
+                            int32_t *best_schedule, double *best_ms, void *stream) {
+    return tune_solve(fw::DType::F64, dist, next, n, ld, reps, best_block, best_schedule, best_ms, stream);
+}
+
 fw_status fw_tune_solve_i32(int32_t *dist, int32_t *next, int64_t n, int64_t ld, int32_t reps, int32_t *best_block,
                             int32_t *best_schedule, double *best_ms, void *stream) {
     return tune_solve(fw::DType::I32, dist, next, n, ld, reps, best_block, best_schedule, best_ms, stream);
@@ -534,6 +546,19 @@ fw_status fw_solve_batched_i32(int32_t *dist, int32_t *next, const int64_t *d_of
 fw_status fw_solve_batched_f32(float *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
                                int32_t batch, int32_t n_max, const fw_options *opt, void *stream) {
     return solve_batched(fw::DType::F32, dist, next, d_offset, d_n, batch, n_max, opt, stream);
+}
+
+fw_status fw_solve_batched_f64(double *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
+                               int32_t batch, int32_t n_max, const fw_options *opt, void *stream) {
+    return solve_batched(fw::DType::F64, dist, next, d_offset, d_n, batch, n_max, opt, stream);
+}
+
+fw_status fw_solve_f64(double *dist, int32_t *next, int64_t n, int64_t ld, void *stream) {
+    return solve(fw::DType::F64, dist, next, n, ld, nullptr, stream);
+}
+
+fw_status fw_solve_ex_f64(double *dist, int32_t *next, int64_t n, int64_t ld, const fw_options *opt, void *stream) {
+    return solve(fw::DType::F64, dist, next, n, ld, opt, stream);
 }
 
 fw_status fw_solve_i32(int32_t *dist, int32_t *next, int64_t n, int64_t ld, void *stream) {

@@ -9,7 +9,8 @@ namespace fw {
 constexpr int kTile = 128;     // output tile edge of the min-plus kernel
 constexpr int kThreads = 256;  // threads per workgroup (four wave64s)
 
-enum class DType { I32, F32 };
+enum class DType { I32, F32, F64 };
+inline int dtype_bytes(DType d) { return d == DType::F64 ? 8 : 4; }
 
 // Per-device scratch owned by the library (a few words).
 struct DeviceWork {

@@ -24,8 +24,9 @@
 // comparison that choice is the same in every schedule and tile order.
 //
 // Arithmetic: int32 distances run as uint32 (INF = 2^30, INF + INF = 2^31
-// does not wrap); float32 as IEEE single.  Every relaxation is a single
-// rounded add, so the k order does not change any distance.
+// does not wrap); float32 and float64 as IEEE single / double.  Every
+// relaxation is a single rounded add, so the k order does not change any
+// distance.
 #include "fw_internal.h"
 
 namespace fw {
@@ -48,6 +49,21 @@ template <> struct Arith<float> {
     static __device__ __forceinline__ float inf() { return __builtin_inff(); }
     static __device__ __forceinline__ float mn(float a, float b) { return __builtin_fminf(a, b); }
 };
+template <> struct Arith<double> {
+    using V4 = double4;
+    static __device__ __forceinline__ double inf() { return __builtin_inf(); }
+    static __device__ __forceinline__ double mn(double a, double b) { return __builtin_fmin(a, b); }
+};
+
+// Launch bounds.  Threads per workgroup of the min-plus code: 512 for the
+// deferred successor variant, else 256.  Minimum waves per SIMD: 32-bit
+// distances fit 128 VGPRs at four waves; 64-bit ones need twice the
+// registers and run two waves (one for the eager variant).
+template <typename U, int ARGMIN> struct Occ {
+    static constexpr int threads = ARGMIN == 2 ? 512 : 256;
+    static constexpr int waves = sizeof(U) == 8 ? (ARGMIN == 1 ? 1 : 2) : (ARGMIN == 1 ? 1 : 4);
+    static constexpr int waves_standalone = sizeof(U) == 8 ? (ARGMIN == 2 ? 2 : 1) : (ARGMIN == 2 ? 4 : 1);
+};
 
 // ------------------------------------------------------------------ init
 // Normalise the input in place: diagonal 0, int32 entries >= 2^30 (or < 0)
@@ -65,6 +81,12 @@ __device__ __forceinline__ float norm_weight(float v, bool diag, bool &bad) {
     if (diag) return 0.0f;
     if (v != v) return __builtin_inff();
     return v == 0.0f ? 0.0f : v;
+}
+__device__ __forceinline__ double norm_weight(double v, bool diag, bool &bad) {
+    bad = !diag && (v < 0.0 || v != v);
+    if (diag) return 0.0;
+    if (v != v) return __builtin_inf();
+    return v == 0.0 ? 0.0 : v;
 }
 
 template <typename U>
@@ -98,8 +120,8 @@ __global__ __launch_bounds__(256) void init_kernel(U *__restrict__ D, int32_t *_
 // copy of the block (NXLDS = true: fewer registers, inside the persistent
 // kernel); both give the same bits.
 template <typename U, int BS, bool NXLDS> struct Phase1Smem {
-    U rowb[2][BS];
-    U colb[2][BS];
+    alignas(16) U rowb[2][BS];
+    alignas(16) U colb[2][BS];
     int32_t nxb[NXLDS ? 1 : 2][BS];              // published successor column
     int32_t nx[NXLDS ? BS : 1][BS + 1];          // odd pitch: column reads hit distinct banks
 };
@@ -279,9 +301,6 @@ __device__ __forceinline__ void lds_operands(const U (*As)[LDP], const U (*Bs)[L
     }
 }
 
-template <typename U> __device__ __forceinline__ int as_int(U v) { return __builtin_bit_cast(int, v); }
-template <typename U> __device__ __forceinline__ U from_int(int v) { return __builtin_bit_cast(U, v); }
-
 // Orders LDS traffic between lanes of one wave (the LDS executes a wave's
 // accesses in issue order; this keeps the compiler from reordering them).
 __device__ __forceinline__ void wave_sync() {
@@ -308,8 +327,8 @@ template <typename U, int ARGMIN> struct MinplusSmem {
     static constexpr int NT = (ARGMIN == 2) ? 512 : 256;
     static constexpr int QCAP = 128;                           // queue entries per wave
     static constexpr int Q = (ARGMIN == 2) ? NT / 64 * QCAP : 1;
-    U As[KC][LDP];                                            // As[k][i] = A[i][k]
-    U Bs[KC][LDP];                                            // Bs[k][j] = B[k][j]
+    alignas(4 * sizeof(U)) U As[KC][LDP];                     // As[k][i] = A[i][k]
+    alignas(4 * sizeof(U)) U Bs[KC][LDP];                     // Bs[k][j] = B[k][j]
     uint32_t kst[ARGMIN == 2 ? kTile * kTile / 4 : 1];       // improving k per entry (bytes)
     uint32_t qpos[Q];                                         // queued entry: i | j << 8
     U qval[Q];                                                // its chunk minimum
@@ -679,7 +698,7 @@ __device__ __forceinline__ void minplus_tile(U *__restrict__ D, int32_t *__restr
 }
 
 template <typename U, int ARGMIN, int PHASE, bool VEC>
-__global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 2 ? 4 : 1) void minplus_kernel(
+__global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves_standalone)) void minplus_kernel(
         U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int K, int BS, int nt) {
     __shared__ MinplusSmem<U, ARGMIN> sm;
     const int64_t b0 = (int64_t)K * BS;
@@ -976,7 +995,7 @@ __device__ __forceinline__ bool persistent_solve(U *__restrict__ D, int32_t *__r
 }
 
 template <typename U, int ARGMIN, bool VEC>
-__global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 1 ? 1 : 4) void persistent_kernel(
+__global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves)) void persistent_kernel(
         U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int R, int nt,
         int *__restrict__ wsp, int *__restrict__ err, uint64_t timeout_ticks) {
     __shared__ PersistSmem<U, ARGMIN> sm;
@@ -1106,7 +1125,7 @@ __global__ __launch_bounds__(256) void batch_init_kernel(U *__restrict__ D, int3
 // items of their own graph that running members have taken, so the launch
 // needs no co-resident grid.  A one-tile graph is one phase-1 closure.
 template <typename U, int ARGMIN>
-__global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256, ARGMIN == 1 ? 1 : 4) void batched_team_kernel(
+__global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves)) void batched_team_kernel(
         U *__restrict__ D, int32_t *__restrict__ NX, const int64_t *__restrict__ off,
         const int32_t *__restrict__ nv, const int *__restrict__ perm, const int *__restrict__ cum, int batch,
         int n_max, int *__restrict__ ticket, int *__restrict__ wsbase, int64_t ws_stride, int *__restrict__ err,
@@ -1349,22 +1368,35 @@ int64_t batched_workspace_ints(int batch, int n_max, int team_cap) {
 }
 
 hipError_t launch_batched(const BatchPlan &b) {
-    return b.dtype == DType::I32 ? batched_dispatch<uint32_t>(b) : batched_dispatch<float>(b);
+    switch (b.dtype) {
+    case DType::I32: return batched_dispatch<uint32_t>(b);
+    case DType::F32: return batched_dispatch<float>(b);
+    default: return batched_dispatch<double>(b);
+    }
 }
 
 int64_t persistent_workspace_ints(int rounds, int nt) { return persist_ws_ints(rounds, nt); }
 
 hipError_t launch_persistent(const Plan &p) {
-    return p.dtype == DType::I32 ? persistent_dispatch<uint32_t>(p) : persistent_dispatch<float>(p);
+    switch (p.dtype) {
+    case DType::I32: return persistent_dispatch<uint32_t>(p);
+    case DType::F32: return persistent_dispatch<float>(p);
+    default: return persistent_dispatch<double>(p);
+    }
 }
 
 hipError_t launch_init(const Plan &p) {
-    return p.dtype == DType::I32 ? init_t<uint32_t>(p) : init_t<float>(p);
+    switch (p.dtype) {
+    case DType::I32: return init_t<uint32_t>(p);
+    case DType::F32: return init_t<float>(p);
+    default: return init_t<double>(p);
+    }
 }
 
 hipError_t launch_phase1(const Plan &p, int K) {
     if (p.dtype == DType::I32) return p.next ? phase1_t<uint32_t, true>(p, K) : phase1_t<uint32_t, false>(p, K);
-    return p.next ? phase1_t<float, true>(p, K) : phase1_t<float, false>(p, K);
+    if (p.dtype == DType::F32) return p.next ? phase1_t<float, true>(p, K) : phase1_t<float, false>(p, K);
+    return p.next ? phase1_t<double, true>(p, K) : phase1_t<double, false>(p, K);
 }
 
 template <typename U>
@@ -1374,11 +1406,19 @@ hipError_t minplus_dispatch(const Plan &p, int K, int phase) {
 }
 
 hipError_t launch_phase2(const Plan &p, int K) {
-    return p.dtype == DType::I32 ? minplus_dispatch<uint32_t>(p, K, 2) : minplus_dispatch<float>(p, K, 2);
+    switch (p.dtype) {
+    case DType::I32: return minplus_dispatch<uint32_t>(p, K, 2);
+    case DType::F32: return minplus_dispatch<float>(p, K, 2);
+    default: return minplus_dispatch<double>(p, K, 2);
+    }
 }
 
 hipError_t launch_phase3(const Plan &p, int K) {
-    return p.dtype == DType::I32 ? minplus_dispatch<uint32_t>(p, K, 3) : minplus_dispatch<float>(p, K, 3);
+    switch (p.dtype) {
+    case DType::I32: return minplus_dispatch<uint32_t>(p, K, 3);
+    case DType::F32: return minplus_dispatch<float>(p, K, 3);
+    default: return minplus_dispatch<double>(p, K, 3);
+    }
 }
 
 }  // namespace fw

@@ -23,7 +23,8 @@ def gpu_solve(W, next_hop=True, block=0, schedule=0, ld=None, stream=None, flags
     import torch
     import paper_2403_18619_amd as fw
     n = W.shape[0]
-    dt = torch.int32 if W.dtype == np.int32 else torch.float32
+    dt = {np.dtype(np.int32): torch.int32, np.dtype(np.float32): torch.float32,
+          np.dtype(np.float64): torch.float64}[W.dtype]
     ld = n if ld is None else ld
     D = torch.empty((n, max(ld, 1)), dtype=dt, device="cuda")[:, :n]
     D.copy_(torch.from_numpy(np.ascontiguousarray(W)))

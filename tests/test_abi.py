@@ -113,3 +113,13 @@ def test_tuners_reject_bad_arguments_on_host():
 def test_batched_rejects_negative_team():
     opt = B.fw_options(0, 0, 0, 0, -2)
     assert fw.lib.fw_solve_batched_f32(FAKE, None, FAKE, FAKE, 4, 16, ctypes.byref(opt), None) == fw.FW_ERR_INVALID_ARG
+
+
+def test_f64_entry_points_reject_bad_arguments_on_host():
+    assert fw.lib.fw_solve_f64(FAKE, None, -1, 4, None) == fw.FW_ERR_INVALID_ARG
+    assert fw.lib.fw_solve_f64(FAKE, None, 8, 7, None) == fw.FW_ERR_INVALID_ARG
+    assert fw.lib.fw_solve_f64(FAKE, None, 1 << 30, 1 << 59, None) == fw.FW_ERR_INVALID_ARG   # 8-byte elements overflow
+    assert fw.lib.fw_solve_f64(None, None, 0, 0, None) == fw.FW_OK
+    opt = B.fw_options(48, 0, 0, 0, 0)
+    assert fw.lib.fw_solve_ex_f64(FAKE, None, 16, 16, ctypes.byref(opt), None) == fw.FW_ERR_INVALID_ARG
+    assert fw.lib.fw_solve_batched_f64(FAKE, None, FAKE, FAKE, -1, 16, None, None) == fw.FW_ERR_INVALID_ARG

@@ -211,3 +211,19 @@ def test_validator_rejects_broken_outputs():
     assert oracle.validate_walk(W, D, NX2)[0] >= 1
     NX3 = NX.copy(); NX3[0, 0] = -1
     assert oracle.validate_walk(W, D, NX3)[0] >= 1
+
+
+def test_validator_f64_accepts_oracle_and_rejects_broken():
+    W = synth.graph_f32(60, 41, 0.3, 0.1, 10.0).astype(np.float64)
+    D, NX = oracle.fw_f64(W)
+    assert oracle.validate_walk(W, D, NX, rtol=1e-12)[0] == 0
+    D2 = D.copy()
+    i, j = np.argwhere(np.isfinite(D2) & (D2 > 0))[5]
+    D2[i, j] *= 1 + 1e-9                                   # a sum that no longer matches
+    assert oracle.validate_walk(W, D2, NX, rtol=1e-12)[1][2] == 4
+    N2 = NX.copy()
+    N2[i, j] = i                                           # a walk that stays put
+    assert oracle.validate_walk(W, D, N2, rtol=1e-12)[1][2] == 3
+    D3 = D.copy()
+    D3[0, 0] = 1.0
+    assert oracle.validate_walk(W, D3, NX, rtol=1e-12)[1][2] == 1
