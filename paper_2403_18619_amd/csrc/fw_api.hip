@@ -203,6 +203,11 @@ fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
         s = persistent_plan(p, (o.flags & FW_FLAG_TEST_TIMEOUT) != 0);
         if (s != FW_OK) return s;
     }
+    if (!persistent && dt == fw::DType::I32 && next && !p.eager_argmin) {
+        // band maxima for the packed-key phase 3 (two round parities)
+        s = grow_ints(&p.work->bmax, &p.work->bmax_ints, 4 * (int64_t)p.nt, "band maxima");
+        if (s != FW_OK) return s;
+    }
     hipError_t e = timed(tm, 0, p.stream, [&] { return fw::launch_init(p); });
     if (e != hipSuccess) return hip_fail(e, "init launch");
     if (persistent) {

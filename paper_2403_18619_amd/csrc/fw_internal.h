@@ -21,6 +21,8 @@ struct DeviceWork {
     int64_t batch_ints = 0;    // its capacity
     int *bwd = nullptr;        // backward, large n: per-workgroup vertex arrays
     int64_t bwd_ints = 0;      // its capacity
+    int *bmax = nullptr;       // three-launch schedule: band maxima, 4 nt ints
+    int64_t bmax_ints = 0;     // its capacity
 };
 
 struct Plan {

@@ -27,6 +27,8 @@
 // does not wrap); float32 and float64 as IEEE single / double.  Every
 // relaxation is a single rounded add, so the k order does not change any
 // distance.
+#include <type_traits>
+
 #include "fw_internal.h"
 
 namespace fw {
@@ -323,6 +325,21 @@ __device__ __forceinline__ void wave_sync() {
 //      winning k is kept in an LDS byte matrix.
 // Variants 1 and 2 select the same k: the first one, in increasing order,
 // that reaches the final minimum when that minimum beats the old value.
+//
+// Packed keys (int32 distances, variant 2, phase 3).  When every finite
+// entry of the round's two operand panels is below 2^22, a phase-3 tile runs
+// the distances-only loop on 32-bit keys that carry the successor choice:
+//   A' = min(a, S) << 8,   B'[k] = (min(b, S) << 8) | (2k + 1),   S = 2^23 - 1
+// (k = position in the round, 0..127), the running value starts as
+// min(C, S) << 8.  A finite + finite sum stays below S, so its key orders
+// exactly like the sum, ties broken by the smaller k; a sum with an "infinite"
+// operand clamps to at least S and never beats anything (its true value is
+// infinite).  A key below the initial one means a strict improvement, and its
+// low bit -- 1 in every candidate, 0 in the initial value -- records that it
+// happened; the minimum key also names the first k reaching the minimum, the
+// same k as the other variants.  No chunk-end search is needed.  Each row
+// and column band tile publishes the largest finite entry it holds (per round
+// parity) for the phase-3 tiles to test.
 template <typename U, int ARGMIN> struct MinplusSmem {
     static constexpr int NT = (ARGMIN == 2) ? 512 : 256;
     static constexpr int QCAP = 128;                           // queue entries per wave
@@ -333,7 +350,15 @@ template <typename U, int ARGMIN> struct MinplusSmem {
     uint32_t qpos[Q];                                         // queued entry: i | j << 8
     U qval[Q];                                                // its chunk minimum
     int qmin[ARGMIN == 2 ? NT : 1];                           // per-entry search result
+    uint32_t bmax_s;                                          // band tile: largest finite entry
 };
+
+constexpr uint32_t kPackLimit = 1u << 22;     // operand panels below this: packed keys
+constexpr uint32_t kPackSat = (1u << 23) - 1; // S: operands clamp here
+__device__ __forceinline__ uint32_t pack_a(uint32_t a) { return (a < kPackSat ? a : kPackSat) << 8; }
+__device__ __forceinline__ uint32_t pack_b(uint32_t b, int k) {
+    return ((b < kPackSat ? b : kPackSat) << 8) | (uint32_t)(2 * k + 1);
+}
 
 // Where the tile of a min-plus launch lies.  mode 0: remainder (phase 3),
 // 1: row band, 2: column band (phase 2).  Returns false when every row or
@@ -356,10 +381,14 @@ __device__ __forceinline__ bool band_tile(int mode, int64_t idx, int64_t n, int6
 }
 
 // One 128 x 128 tile of C <- min(C, A (x) B) over the round's band.
-template <typename U, int ARGMIN, bool VEC>
-__device__ __forceinline__ void minplus_tile(U *__restrict__ D, int32_t *__restrict__ NX, int64_t n,
-                                             int64_t ld, int K, int BS, int mode, int64_t row0,
-                                             int64_t col0, MinplusSmem<U, ARGMIN> &sm) {
+// bmax (may be null): per-round-parity band maxima, 2 x 2 x nt ints
+// (row band tiles, then column band tiles), read by phase-3 tiles and written
+// by band tiles when packed keys apply (int32, variant 2).
+template <typename U, int ARGMIN, bool VEC, bool PACKED>
+__device__ __forceinline__ void minplus_tile_impl(U *__restrict__ D, int32_t *__restrict__ NX, int64_t n,
+                                                  int64_t ld, int K, int BS, int mode, int64_t row0,
+                                                  int64_t col0, MinplusSmem<U, ARGMIN> &sm,
+                                                  int *__restrict__ bmax, int nt) {
     constexpr int NT = MinplusSmem<U, ARGMIN>::NT;
     using G = Geo<NT>;
     constexpr int CPT = G::cpt;
@@ -383,6 +412,12 @@ __device__ __forceinline__ void minplus_tile(U *__restrict__ D, int32_t *__restr
     const int rows_valid = (mode == 1) ? bk : (int)imin64(kTile, n - row0);
     const int cols_valid = (mode == 2) ? bk : (int)imin64(kTile, n - col0);
     constexpr bool use_vec = VEC;
+    constexpr bool PACKABLE = ARGMIN == 2 && std::is_same<U, uint32_t>::value;
+    constexpr bool fast = PACKABLE && PACKED;       // packed keys for this tile
+    int *const bm = PACKABLE && bmax ? bmax + (K & 1) * 2 * nt : nullptr;
+    if constexpr (PACKABLE && !PACKED) {
+        if (t == 0) sm.bmax_s = 0;
+    }
 
     // ---- load C
     U acc[8][CPT];
@@ -405,6 +440,12 @@ __device__ __forceinline__ void minplus_tile(U *__restrict__ D, int32_t *__restr
             for (int e = 0; e < 4; ++e) acc[r][4 * g + e] = v[e];
         }
     }
+    if constexpr (fast) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) acc[r][c] = pack_a((uint32_t)acc[r][c]);
+    }
     int32_t idx[8][CPT];    // improving k (-1: none), later the new successor
     if (ARGMIN == 1) {
 #pragma unroll
@@ -412,7 +453,7 @@ __device__ __forceinline__ void minplus_tile(U *__restrict__ D, int32_t *__restr
 #pragma unroll
             for (int c = 0; c < CPT; ++c) idx[r][c] = -1;
     }
-    if (ARGMIN == 2) {
+    if (ARGMIN == 2 && !fast) {
         for (int q = t; q < kTile * kTile / 4; q += NT) kst[q] = 0xFFFFFFFFu;
         for (int q = t; q < G::waves * 64; q += NT) qmin[q] = 0xFF;
     }
@@ -440,6 +481,10 @@ __device__ __forceinline__ void minplus_tile(U *__restrict__ D, int32_t *__restr
 #pragma unroll
                     for (int e = 0; e < 4; ++e) v[e] = Arith<U>::inf();
                 }
+                if constexpr (fast) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] = pack_a(v[e]);
+                }
 #pragma unroll
                 for (int e = 0; e < 4; ++e) As[kk + e][a_il] = v[e];
             }
@@ -457,6 +502,10 @@ __device__ __forceinline__ void minplus_tile(U *__restrict__ D, int32_t *__restr
 #pragma unroll
                     for (int e = 0; e < 4; ++e) v[e] = Arith<U>::inf();
                 }
+                if constexpr (fast) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] = pack_b(v[e], kc + b_kk);
+                }
                 typename Arith<U>::V4 w;
                 w.x = v[0]; w.y = v[1]; w.z = v[2]; w.w = v[3];
                 *reinterpret_cast<typename Arith<U>::V4 *>(&Bs[b_kk][jl]) = w;
@@ -464,7 +513,20 @@ __device__ __forceinline__ void minplus_tile(U *__restrict__ D, int32_t *__restr
         }
         __syncthreads();
 
-        if constexpr (ARGMIN == 1) {
+        if constexpr (fast) {
+#pragma unroll 1
+            for (int kk = 0; kk < KC; kk += 2) {
+                U a[8], b[CPT], a2[8], b2[CPT];
+                lds_operands<U, NT>(As, Bs, kk, tx, ty, a, b);
+                lds_operands<U, NT>(As, Bs, kk + 1, tx, ty, a2, b2);
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c)
+                        acc[r][c] = Arith<U>::mn(acc[r][c], Arith<U>::mn(a[r] + b[c], a2[r] + b2[c]));
+                }
+            }
+        } else if constexpr (ARGMIN == 1) {
 #pragma unroll 2
             for (int kk = 0; kk < KC; ++kk) {
                 U a[8], b[CPT];
@@ -616,7 +678,18 @@ __device__ __forceinline__ void minplus_tile(U *__restrict__ D, int32_t *__restr
     // column band A is C itself).  Afterwards idx holds the new successor of
     // an improved entry (>= 0: its A entry is finite) and -1 elsewhere.
     if (NEXT) {
-        if (ARGMIN == 2) {
+        if constexpr (fast) {
+            // packed keys: bit 0 = improved, bits 1..7 = k, bits 8.. = value
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    const uint32_t key = (uint32_t)acc[r][c];
+                    idx[r][c] = (key & 1u) ? (int32_t)((key >> 1) & 127u) : -1;
+                    acc[r][c] = (U)(key >> 8);
+                }
+            }
+        } else if (ARGMIN == 2) {
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
@@ -638,6 +711,25 @@ __device__ __forceinline__ void minplus_tile(U *__restrict__ D, int32_t *__restr
             }
         }
         __syncthreads();
+    }
+
+    // ---- a band tile publishes its largest finite entry (packed keys)
+    if constexpr (PACKABLE && !PACKED) {
+        if (mode != 0 && bm) {
+            uint32_t m = 0;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const bool rv = G::row_off(tye, r) < rows_valid;
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    const uint32_t v = (uint32_t)acc[r][c];
+                    if (rv && G::col_off(txe, c) < cols_valid && v < kInfU) m = v > m ? v : m;
+                }
+            }
+            atomicMax(&sm.bmax_s, m);
+            __syncthreads();
+            if (t == 0) bm[(mode == 1 ? 0 : nt) + (int)((mode == 1 ? col0 : row0) / kTile)] = (int)sm.bmax_s;
+        }
     }
 
     // ---- store (rows / columns of the band itself are not part of phase 3)
@@ -697,9 +789,30 @@ __device__ __forceinline__ void minplus_tile(U *__restrict__ D, int32_t *__restr
     }
 }
 
+// One 128 x 128 tile: packed keys when the round's operand panels allow them
+// (int32 with successors, phase 3), the general form otherwise.
+template <typename U, int ARGMIN, bool VEC>
+__device__ __forceinline__ void minplus_tile(U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld,
+                                             int K, int BS, int mode, int64_t row0, int64_t col0,
+                                             MinplusSmem<U, ARGMIN> &sm, int *__restrict__ bmax, int nt) {
+    if constexpr (ARGMIN == 2 && std::is_same<U, uint32_t>::value) {
+        if (mode == 0 && bmax) {
+            const int *bm = bmax + (K & 1) * 2 * nt;
+            const uint32_t ma = (uint32_t)bm[nt + (int)(row0 / kTile)];   // A = column band tile (I, K)
+            const uint32_t mb = (uint32_t)bm[(int)(col0 / kTile)];        // B = row band tile (K, J)
+            if (ma < kPackLimit && mb < kPackLimit) {
+                minplus_tile_impl<U, ARGMIN, VEC, true>(D, NX, n, ld, K, BS, mode, row0, col0, sm, bmax, nt);
+                return;
+            }
+        }
+    }
+    minplus_tile_impl<U, ARGMIN, VEC, false>(D, NX, n, ld, K, BS, mode, row0, col0, sm, bmax, nt);
+}
+
 template <typename U, int ARGMIN, int PHASE, bool VEC>
 __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves_standalone)) void minplus_kernel(
-        U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int K, int BS, int nt) {
+        U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int K, int BS, int nt,
+        int *__restrict__ bmax) {
     __shared__ MinplusSmem<U, ARGMIN> sm;
     const int64_t b0 = (int64_t)K * BS;
     const int64_t b1 = b0 + imin64((int64_t)BS, n - b0);
@@ -720,7 +833,7 @@ __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves_s
     }
     int64_t row0, col0;
     if (!band_tile(mode, idx, n, b0, b1, nt, row0, col0)) return;
-    minplus_tile<U, ARGMIN, VEC>(D, NX, n, ld, K, BS, mode, row0, col0, sm);
+    minplus_tile<U, ARGMIN, VEC>(D, NX, n, ld, K, BS, mode, row0, col0, sm, bmax, nt);
 }
 
 // ------------------------------------------------------ persistent schedule
@@ -754,13 +867,13 @@ __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves_s
 // wall-clock deadline; on expiry the error word gets code 2 and an abort
 // flag makes every workgroup leave.
 struct PersistWs {
-    int *abort, *diag, *q, *xq, *done, *p2c, *rrd, *crd, *rowf, *colf, *nrow, *ncol;
+    int *abort, *diag, *q, *xq, *done, *p2c, *rrd, *crd, *rowf, *colf, *nrow, *ncol, *bmax;
 };
 
 constexpr int kXcds = 8;        // MI355X: eight XCDs, workgroups dealt round-robin
 
 __host__ __device__ __forceinline__ int64_t persist_ws_ints(int R, int nt) {
-    return 4 + (5 + kXcds) * (int64_t)R + 4 * (int64_t)nt;
+    return 4 + (5 + kXcds) * (int64_t)R + 8 * (int64_t)nt;
 }
 
 __device__ __forceinline__ PersistWs persist_ws(int *w, int R, int nt) {
@@ -777,6 +890,7 @@ __device__ __forceinline__ PersistWs persist_ws(int *w, int R, int nt) {
     p.colf = p.rowf + nt;
     p.nrow = p.colf + nt;
     p.ncol = p.nrow + nt;
+    p.bmax = p.ncol + nt;                      // 2 parities x (row, column) x nt
     return p;
 }
 
@@ -964,7 +1078,7 @@ __device__ __forceinline__ bool persistent_solve(U *__restrict__ D, int32_t *__r
             if (item == 0)
                 phase1_block<U, NEXT, BS, NT, NEXT>(D, NX, n, ld, K, sm.p1);
             else if (work)
-                minplus_tile<U, ARGMIN, VEC>(D, NX, n, ld, K, BS, mode, row0, col0, sm.mp);
+                minplus_tile<U, ARGMIN, VEC>(D, NX, n, ld, K, BS, mode, row0, col0, sm.mp, ws.bmax, nt);
             // ---- publish what later items wait for
             if (item == 0) {
                 publish(lead, ws.diag, K + 1);
@@ -1207,14 +1321,14 @@ __global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256) void batched_kernel(
             const int mode = q < nt ? 1 : 2;
             int64_t row0, col0;
             if (band_tile(mode, q % nt, n, b0, b1, nt, row0, col0)) {
-                minplus_tile<U, ARGMIN, false>(Dg, NXg, n, n, K, BS, mode, row0, col0, sm.mp);
+                minplus_tile<U, ARGMIN, false>(Dg, NXg, n, n, K, BS, mode, row0, col0, sm.mp, nullptr, nt);
                 __syncthreads();
             }
         }
         for (int q = 0; q < nt * nt; ++q) {
             int64_t row0, col0;
             if (band_tile(0, q, n, b0, b1, nt, row0, col0)) {
-                minplus_tile<U, ARGMIN, false>(Dg, NXg, n, n, K, BS, 0, row0, col0, sm.mp);
+                minplus_tile<U, ARGMIN, false>(Dg, NXg, n, n, K, BS, 0, row0, col0, sm.mp, nullptr, nt);
                 __syncthreads();
             }
         }
@@ -1242,14 +1356,15 @@ hipError_t phase1_t(const Plan &p, int K) {
 
 template <typename U, int ARGMIN, bool VEC>
 hipError_t minplus_t(const Plan &p, int K, int phase) {
-    constexpr int NT = (ARGMIN == 2) ? 512 : 256;
+    constexpr int NT = Occ<U, ARGMIN>::threads;
+    int *bmax = (ARGMIN == 2 && std::is_same<U, uint32_t>::value) ? p.work->bmax : nullptr;
     if (phase == 2) {
         hipLaunchKernelGGL((minplus_kernel<U, ARGMIN, 2, VEC>), dim3((unsigned)p.nt, 2), dim3(NT), 0, p.stream,
-                           (U *)p.dist, p.next, p.n, p.ld, K, p.bs, p.nt);
+                           (U *)p.dist, p.next, p.n, p.ld, K, p.bs, p.nt, bmax);
     } else {
         const int64_t tiles = (int64_t)p.nt * p.nt;
         hipLaunchKernelGGL((minplus_kernel<U, ARGMIN, 3, VEC>), dim3((unsigned)(8 * ((tiles + 7) / 8))), dim3(NT),
-                           0, p.stream, (U *)p.dist, p.next, p.n, p.ld, K, p.bs, p.nt);
+                           0, p.stream, (U *)p.dist, p.next, p.n, p.ld, K, p.bs, p.nt, bmax);
     }
     return hipGetLastError();
 }
