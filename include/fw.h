@@ -63,9 +63,15 @@ typedef enum fw_status {
 #define FW_INF_I32 1073741824   /* 2^30: int32 "no edge" and unreachable */
 
 /* Schedules (fw_options.schedule). */
-#define FW_SCHED_AUTO 0         /* library's choice: persistent, except three
-                                   launches for successor solves at n >= 16384 */
-#define FW_SCHED_THREE_LAUNCH 1 /* per round: phase 1, phase 2, phase 3      */
+#define FW_SCHED_AUTO 0         /* library's choice: three launches (or the
+                                   autotuned choice for this size)           */
+#define FW_SCHED_THREE_LAUNCH 1 /* per round: phase 1, phase 2, phase 3; with
+                                   block 128 and >= 3 rounds, phase 3 runs the
+                                   next band first and the next round's
+                                   phases 1-2 run meanwhile on a library-owned
+                                   stream joined back with events (the solve
+                                   stays ordered on `stream`, and may be
+                                   captured in a hipGraph)                   */
 #define FW_SCHED_PERSISTENT 2   /* one launch, per-tile dependency flags;
                                    block size 128 only                       */
 

@@ -23,6 +23,8 @@ struct DeviceWork {
     int64_t bwd_ints = 0;      // its capacity
     int *bmax = nullptr;       // three-launch schedule: band maxima, 4 nt ints
     int64_t bmax_ints = 0;     // its capacity
+    hipStream_t aux = nullptr; // three-launch lookahead: the next round's phases 1-2
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
 };
 
 struct Plan {
@@ -81,7 +83,9 @@ int backward_global_workgroups(const BackwardPlan &b);
 hipError_t launch_init(const Plan &p);
 hipError_t launch_phase1(const Plan &p, int K);
 hipError_t launch_phase2(const Plan &p, int K);
-hipError_t launch_phase3(const Plan &p, int K);
+// part 0: every phase-3 tile of round K; 1: the tiles of band K+1 only;
+// 2: all but those (block size 128)
+hipError_t launch_phase3(const Plan &p, int K, int part = 0);
 hipError_t launch_persistent(const Plan &p);
 int64_t persistent_workspace_ints(int rounds, int nt);
 hipError_t launch_batched(const BatchPlan &b);

@@ -817,13 +817,23 @@ __device__ __forceinline__ void minplus_tile(U *__restrict__ D, int32_t *__restr
 template <typename U, int ARGMIN, int PHASE, bool VEC>
 __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves_standalone)) void minplus_kernel(
         U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int K, int BS, int nt,
-        int *__restrict__ bmax) {
+        int *__restrict__ bmax, int part) {
     __shared__ MinplusSmem<U, ARGMIN> sm;
     const int64_t b0 = (int64_t)K * BS;
     const int64_t b1 = b0 + imin64((int64_t)BS, n - b0);
     int mode;
     int64_t idx;
-    if (PHASE == 3) {
+    if (PHASE == 3 && part == 1) {
+        // the next band's tiles (row and column K+1; block size = tile edge)
+        const int q = (int)blockIdx.x, nx1 = K + 1;
+        if (q < nt) {
+            idx = (int64_t)nx1 * nt + q;
+        } else {
+            if (q - nt == nx1) return;           // (K+1, K+1) is in the row above
+            idx = (int64_t)(q - nt) * nt + nx1;
+        }
+        mode = 0;
+    } else if (PHASE == 3) {
         // Workgroups are dealt to the eight XCDs round-robin; give each XCD a
         // contiguous run of tiles so that tiles sharing a row of A meet in the
         // same L2.
@@ -831,6 +841,7 @@ __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves_s
         const int64_t per = (tiles + 7) / 8;
         idx = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
         if (idx >= tiles) return;
+        if (part == 2 && (idx / nt == K + 1 || idx % nt == K + 1)) return;   // done by part 1
         mode = 0;
     } else {
         mode = 1 + (int)blockIdx.y;
@@ -1361,24 +1372,29 @@ hipError_t phase1_t(const Plan &p, int K) {
     return hipGetLastError();
 }
 
+// phase 2: the band tiles; phase 3: every remaining tile (part 0), only the
+// next band's tiles (part 1) or all but those (part 2).
 template <typename U, int ARGMIN, bool VEC>
-hipError_t minplus_t(const Plan &p, int K, int phase) {
+hipError_t minplus_t(const Plan &p, int K, int phase, int part) {
     constexpr int NT = Occ<U, ARGMIN>::threads;
     int *bmax = (ARGMIN == 2 && std::is_same<U, uint32_t>::value) ? p.work->bmax : nullptr;
     if (phase == 2) {
         hipLaunchKernelGGL((minplus_kernel<U, ARGMIN, 2, VEC>), dim3((unsigned)p.nt, 2), dim3(NT), 0, p.stream,
-                           (U *)p.dist, p.next, p.n, p.ld, K, p.bs, p.nt, bmax);
+                           (U *)p.dist, p.next, p.n, p.ld, K, p.bs, p.nt, bmax, 0);
+    } else if (part == 1) {
+        hipLaunchKernelGGL((minplus_kernel<U, ARGMIN, 3, VEC>), dim3((unsigned)(2 * p.nt)), dim3(NT), 0, p.stream,
+                           (U *)p.dist, p.next, p.n, p.ld, K, p.bs, p.nt, bmax, 1);
     } else {
         const int64_t tiles = (int64_t)p.nt * p.nt;
         hipLaunchKernelGGL((minplus_kernel<U, ARGMIN, 3, VEC>), dim3((unsigned)(8 * ((tiles + 7) / 8))), dim3(NT),
-                           0, p.stream, (U *)p.dist, p.next, p.n, p.ld, K, p.bs, p.nt, bmax);
+                           0, p.stream, (U *)p.dist, p.next, p.n, p.ld, K, p.bs, p.nt, bmax, part);
     }
     return hipGetLastError();
 }
 
 template <typename U, int ARGMIN>
-hipError_t minplus_v(const Plan &p, int K, int phase) {
-    return p.vec ? minplus_t<U, ARGMIN, true>(p, K, phase) : minplus_t<U, ARGMIN, false>(p, K, phase);
+hipError_t minplus_v(const Plan &p, int K, int phase, int part) {
+    return p.vec ? minplus_t<U, ARGMIN, true>(p, K, phase, part) : minplus_t<U, ARGMIN, false>(p, K, phase, part);
 }
 
 template <typename U, int ARGMIN, bool VEC>
@@ -1527,24 +1543,24 @@ hipError_t launch_phase1(const Plan &p, int K) {
 }
 
 template <typename U>
-hipError_t minplus_dispatch(const Plan &p, int K, int phase) {
-    if (!p.next) return minplus_v<U, 0>(p, K, phase);
-    return p.eager_argmin ? minplus_v<U, 1>(p, K, phase) : minplus_v<U, 2>(p, K, phase);
+hipError_t minplus_dispatch(const Plan &p, int K, int phase, int part) {
+    if (!p.next) return minplus_v<U, 0>(p, K, phase, part);
+    return p.eager_argmin ? minplus_v<U, 1>(p, K, phase, part) : minplus_v<U, 2>(p, K, phase, part);
 }
 
 hipError_t launch_phase2(const Plan &p, int K) {
     switch (p.dtype) {
-    case DType::I32: return minplus_dispatch<uint32_t>(p, K, 2);
-    case DType::F32: return minplus_dispatch<float>(p, K, 2);
-    default: return minplus_dispatch<double>(p, K, 2);
+    case DType::I32: return minplus_dispatch<uint32_t>(p, K, 2, 0);
+    case DType::F32: return minplus_dispatch<float>(p, K, 2, 0);
+    default: return minplus_dispatch<double>(p, K, 2, 0);
     }
 }
 
-hipError_t launch_phase3(const Plan &p, int K) {
+hipError_t launch_phase3(const Plan &p, int K, int part) {
     switch (p.dtype) {
-    case DType::I32: return minplus_dispatch<uint32_t>(p, K, 3);
-    case DType::F32: return minplus_dispatch<float>(p, K, 3);
-    default: return minplus_dispatch<double>(p, K, 3);
+    case DType::I32: return minplus_dispatch<uint32_t>(p, K, 3, part);
+    case DType::F32: return minplus_dispatch<float>(p, K, 3, part);
+    default: return minplus_dispatch<double>(p, K, 3, part);
     }
 }
 
