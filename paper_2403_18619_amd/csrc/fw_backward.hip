@@ -11,13 +11,23 @@
 // that reaches j points at parent(u) = NX[u][j].  The edge (u, parent(u)) is
 // on path(i, j) exactly when i lies in u's subtree, so it receives the
 // subtree sum S_j(u) = G[u][j] + the sum of S_j(c) over u's children c.  One
-// workgroup handles one destination (one column of G and NX):
+// wave (graphs of up to 1024 vertices) or one workgroup handles one
+// destination (one column of G and NX):
 //   1. load the column: parent and S_j(u) = G[u][j] per vertex;
 //   2. count each vertex's children (LDS atomics);
 //   3. queue the leaves, then process the queue level by level: a vertex
-//      adds S_j(u) to dW[u][parent(u)] (a global float atomic, since other
-//      destinations use the same edge) and to S_j(parent); the parent joins
-//      the queue when its last child is done.
+//      adds S_j(u) to S_j(parent); the parent joins the queue when its last
+//      child is done;
+//   4. write S_j(u) into dW[u][j], used as scratch (0 for the root, for
+//      unreachable vertices and for vertices never processed).
+// A second pass then works per source row u: the edge (u, v) collects
+// S_j(u) over the destinations j with next[u][j] = v, a scatter-add of the
+// row's sums into an LDS histogram indexed by successor, which then
+// overwrites the row.  Both passes read rows or columns once and the second
+// writes each gradient row once, with no global atomics (a column's float
+// atomics into dW touched one cache line per lane and dominated the time).
+// Graphs above 32768 vertices, whose histogram row does not fit in LDS, add
+// into dW with global atomics instead.
 // Work and traffic are O(n) per destination; a step of the level loop is one
 // tree level.  A successor entry outside [0, n) counts as "no path"; a vertex
 // on a successor cycle never becomes ready and is skipped, so malformed
@@ -49,7 +59,7 @@ template <bool SH> __device__ __forceinline__ void bsync() {
     __syncthreads();
 }
 
-template <bool SH>
+template <bool SH, bool ROWS>
 __device__ void backward_column(const float *__restrict__ G, const int32_t *__restrict__ NX,
                                 float *__restrict__ dW, int64_t ld, int n, int j, int *par, int *cnt,
                                 float *S, int *q, int &tail) {
@@ -82,7 +92,8 @@ __device__ void backward_column(const float *__restrict__ G, const int32_t *__re
             const int u = sld<SH>(&q[x]);
             const int v = sld<SH>(&par[u]);
             const float s = sld<SH>(&S[u]);
-            unsafeAtomicAdd(&dW[(int64_t)u * ld + v], s);
+            if (ROWS) sst<SH>(&cnt[u], -1);                  // processed
+            else unsafeAtomicAdd(&dW[(int64_t)u * ld + v], s);
             if (v != j) {
                 if (SH) atomicAdd(&S[v], s);
                 else unsafeAtomicAdd(&S[v], s);
@@ -91,13 +102,17 @@ __device__ void backward_column(const float *__restrict__ G, const int32_t *__re
         }
         head = end;
     }
+    if (ROWS) {
+        for (int u = t; u < n; u += kBwdThreads)
+            dW[(int64_t)u * ld + j] = sld<SH>(&cnt[u]) == -1 ? sld<SH>(&S[u]) : 0.0f;
+    }
 }
 
 // grid.x = 8 * ceil(columns / 8) workgroups (or fewer for the global form,
 // which then loops), grid.y = graphs.  Workgroups are dealt to the eight XCDs
 // round-robin; the mapping gives each XCD a contiguous run of destinations,
 // so neighbouring columns share cache lines in one L2.
-template <bool SH>
+template <bool SH, bool ROWS>
 __global__ __launch_bounds__(kBwdThreads) void backward_kernel(
         const float *__restrict__ G, const int32_t *__restrict__ NX, float *__restrict__ dW, int64_t n1,
         int64_t ld1, const int64_t *__restrict__ off, const int32_t *__restrict__ nv, int n_cap,
@@ -132,7 +147,124 @@ __global__ __launch_bounds__(kBwdThreads) void backward_kernel(
         q = reinterpret_cast<int *>(S + n_cap);
     }
     for (int64_t j = jb; j < n; j += gridDim.x)
-        backward_column<SH>(G + base, NX + base, dW + base, ld, n, (int)j, par, cnt, S, q, s_tail);
+        backward_column<SH, ROWS>(G + base, NX + base, dW + base, ld, n, (int)j, par, cnt, S, q, s_tail);
+}
+
+// Graphs of at most kBwdWaveMaxN vertices: one wave per destination, four
+// destinations per workgroup, wave-level ordering instead of workgroup
+// barriers (a destination's tree has few levels and few vertices per lane,
+// so barriers and idle lanes dominated the workgroup form).
+constexpr int kBwdWaveMaxN = 1024;
+
+__device__ __forceinline__ void wave_sync_bwd() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(256) void backward_wave_kernel(
+        const float *__restrict__ G, const int32_t *__restrict__ NX, float *__restrict__ dW, int64_t n1,
+        int64_t ld1, const int64_t *__restrict__ off, const int32_t *__restrict__ nv, int n_cap,
+        int *__restrict__ err) {
+    extern __shared__ int bwd_lds[];
+    __shared__ int s_tail[4];
+    int64_t base = 0, ld = ld1;
+    int n = (int)n1;
+    if (off) {
+        n = nv[blockIdx.y];
+        base = off[blockIdx.y];
+        ld = n;
+        if (n < 0 || n > n_cap) {
+            if (threadIdx.x == 0 && blockIdx.x == 0) atomicCAS(err, 0, 3);
+            return;
+        }
+    }
+    if (n <= 1) return;
+    const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    // workgroups are dealt to the XCDs round-robin: each XCD gets a run of
+    // neighbouring destinations, whose columns share cache lines
+    const int per = (int)(gridDim.x / 8);
+    const int grp = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    const int j = grp * 4 + w;
+    if (j >= n) return;                     // the whole wave; no workgroup barrier follows
+    int *par = bwd_lds + (int64_t)w * 4 * n_cap;
+    int *cnt = par + n_cap;
+    float *S = reinterpret_cast<float *>(cnt + n_cap);
+    int *q = reinterpret_cast<int *>(S + n_cap);
+    int &tail = s_tail[w];
+    const float *Gg = G + base;
+    const int32_t *Ng = NX + base;
+    float *dWg = dW + base;
+    if (lane == 0) tail = 0;
+    for (int u = lane; u < n; u += 64) {
+        const int64_t o = (int64_t)u * ld + j;
+        const int v = Ng[o];
+        const bool on = u != j && v >= 0 && v < n;
+        par[u] = on ? v : -1;
+        S[u] = on ? Gg[o] : 0.0f;
+        cnt[u] = 0;
+    }
+    wave_sync_bwd();
+    for (int u = lane; u < n; u += 64) {
+        const int v = par[u];
+        if (v >= 0 && v != j) atomicAdd(&cnt[v], 1);
+    }
+    wave_sync_bwd();
+    for (int u = lane; u < n; u += 64)
+        if (par[u] >= 0 && cnt[u] == 0) q[atomicAdd(&tail, 1)] = u;
+    int head = 0;
+    for (;;) {
+        wave_sync_bwd();
+        const int end = tail;
+        if (head >= end) break;
+        for (int x = head + lane; x < end; x += 64) {
+            const int u = q[x];
+            const int v = par[u];
+            const float sv = S[u];
+            cnt[u] = -1;                                      // processed
+            if (v != j) {
+                atomicAdd(&S[v], sv);
+                if (atomicSub(&cnt[v], 1) == 1) q[atomicAdd(&tail, 1)] = v;
+            }
+        }
+        head = end;
+    }
+    wave_sync_bwd();
+    for (int u = lane; u < n; u += 64) dWg[(int64_t)u * ld + j] = cnt[u] == -1 ? S[u] : 0.0f;
+}
+
+// Second pass: row u of every graph.  T[u][j] = S_j(u) (the first pass's
+// sums, stored in dW) is scatter-added into bins[next[u][j]], then the row
+// becomes the gradient.  j == u and successors outside [0, n) add nothing.
+constexpr int kBwdRowsMaxN = 32768;     // 4 bytes of LDS per vertex
+
+__global__ __launch_bounds__(256) void backward_rows_kernel(const int32_t *__restrict__ NX, float *__restrict__ dW,
+                                                            int64_t n1, int64_t ld1, const int64_t *__restrict__ off,
+                                                            const int32_t *__restrict__ nv, int n_cap) {
+    extern __shared__ float bins[];
+    int64_t base = 0, ld = ld1;
+    int n = (int)n1;
+    if (off) {
+        n = nv[blockIdx.y];
+        base = off[blockIdx.y];
+        ld = n;
+        if (n < 0 || n > n_cap) return;                      // reported by the first pass
+    }
+    const int t = threadIdx.x;
+    for (int64_t u = blockIdx.x; u < n; u += gridDim.x) {
+        const int32_t *nrow = NX + base + u * ld;
+        float *drow = dW + base + u * ld;
+        for (int v = t; v < n; v += 256) bins[v] = 0.0f;
+        __syncthreads();
+        for (int jj = t; jj < n; jj += 256) {
+            const int v = nrow[jj];
+            const float sv = drow[jj];
+            if (jj != (int)u && v >= 0 && v < n && sv != 0.0f) atomicAdd(&bins[v], sv);
+        }
+        __syncthreads();
+        for (int v = t; v < n; v += 256) drow[v] = bins[v];
+        __syncthreads();
+    }
 }
 
 // dW = 0 over each graph's n x n block (rows of length n at stride ld).
@@ -164,22 +296,42 @@ int backward_global_workgroups(const BackwardPlan &b) {
 
 hipError_t launch_backward(const BackwardPlan &b) {
     const unsigned graphs = b.off ? (unsigned)b.batch : 1u;
-    const unsigned zx = (unsigned)(b.n_cap < 4096 ? b.n_cap : 4096);
-    hipLaunchKernelGGL(zero_grad_kernel, dim3(zx, graphs), dim3(256), 0, b.stream, b.dW, b.n, b.ld, b.off, b.nv,
-                       b.n_cap);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (b.n_cap <= kBackwardLdsMaxN) {
+    const bool rows = b.n_cap <= kBwdRowsMaxN;
+    hipError_t e;
+    if (!rows) {                                      // global atomics need a zeroed dW
+        const unsigned zx = (unsigned)(b.n_cap < 4096 ? b.n_cap : 4096);
+        hipLaunchKernelGGL(zero_grad_kernel, dim3(zx, graphs), dim3(256), 0, b.stream, b.dW, b.n, b.ld, b.off, b.nv,
+                           b.n_cap);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (b.n_cap <= kBwdWaveMaxN) {
+        const int groups = (b.n_cap + 3) / 4;
+        const unsigned gx = (unsigned)(8 * ((groups + 7) / 8));
+        const size_t lds = (size_t)4 * 16 * b.n_cap;
+        hipLaunchKernelGGL(backward_wave_kernel, dim3(gx, graphs), dim3(256), lds, b.stream, b.G, b.NX, b.dW, b.n,
+                           b.ld, b.off, b.nv, b.n_cap, b.err);
+    } else if (b.n_cap <= kBackwardLdsMaxN) {
         const unsigned gx = (unsigned)(8 * ((b.n_cap + 7) / 8));
         const size_t lds = (size_t)16 * b.n_cap;
-        hipLaunchKernelGGL(backward_kernel<true>, dim3(gx, graphs), dim3(kBwdThreads), lds, b.stream, b.G, b.NX,
-                           b.dW, b.n, b.ld, b.off, b.nv, b.n_cap, nullptr, b.err);
+        hipLaunchKernelGGL((backward_kernel<true, true>), dim3(gx, graphs), dim3(kBwdThreads), lds, b.stream, b.G,
+                           b.NX, b.dW, b.n, b.ld, b.off, b.nv, b.n_cap, nullptr, b.err);
     } else {
         const unsigned gx = (unsigned)backward_global_workgroups(b);
-        hipLaunchKernelGGL(backward_kernel<false>, dim3(gx, graphs), dim3(kBwdThreads), 0, b.stream, b.G, b.NX,
-                           b.dW, b.n, b.ld, b.off, b.nv, b.n_cap, b.scratch, b.err);
+        if (rows)
+            hipLaunchKernelGGL((backward_kernel<false, true>), dim3(gx, graphs), dim3(kBwdThreads), 0, b.stream, b.G,
+                               b.NX, b.dW, b.n, b.ld, b.off, b.nv, b.n_cap, b.scratch, b.err);
+        else
+            hipLaunchKernelGGL((backward_kernel<false, false>), dim3(gx, graphs), dim3(kBwdThreads), 0, b.stream, b.G,
+                               b.NX, b.dW, b.n, b.ld, b.off, b.nv, b.n_cap, b.scratch, b.err);
     }
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (rows) {
+        const unsigned rx = (unsigned)(b.n_cap < 8192 ? b.n_cap : 8192);
+        hipLaunchKernelGGL(backward_rows_kernel, dim3(rx, graphs), dim3(256), (size_t)4 * b.n_cap, b.stream, b.NX,
+                           b.dW, b.n, b.ld, b.off, b.nv, b.n_cap);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace fw

@@ -65,11 +65,13 @@ def test_backward_matches_reference(recipe, n):
 
 
 def test_backward_padded_rows_and_large_n_scratch_path():
-    """ld > n, and n above the LDS bound (global per-workgroup arrays)."""
-    log("case backward ld padding + n=4500")
+    """ld > n; the three kernel forms: one wave per destination (n <= 1024),
+    one workgroup with LDS arrays (n <= 4096), one workgroup with global
+    arrays (above)."""
+    log("case backward ld padding + n=2000 + n=4500")
     import torch
     import paper_2403_18619_amd as fw
-    for n, ld in ((300, 333), (4500, 4500)):
+    for n, ld in ((300, 333), (2000, 2003), (4500, 4500)):
         W = synth.graph_f32(n, 901, 0.002 if n > 1000 else 0.3, 0.1, 10.0)
         G = synth.normal_f32(n, n, 902)
         _, NX = gpu_solve(W)
