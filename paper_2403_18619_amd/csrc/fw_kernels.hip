@@ -27,6 +27,7 @@
 // does not wrap); float32 and float64 as IEEE single / double.  Every
 // relaxation is a single rounded add, so the k order does not change any
 // distance.
+#include <atomic>
 #include <type_traits>
 
 #include "fw_internal.h"
@@ -347,8 +348,8 @@ template <typename U, int ARGMIN> struct alignas(4 * sizeof(U)) MinplusSmem {
     static constexpr int QCAP = 128;                           // queue entries per wave
     static constexpr int Q = (ARGMIN == 2) ? NT / 64 * QCAP : 1;
     // 64-bit entries are read as 32-byte vectors: declare that alignment (for
-    // 32-bit ones the default placement already serves 16-byte reads, and a
-    // declared alignment changes the generated code for the worse)
+    // 32-bit ones the struct's own alignment serves 16-byte reads, and a
+    // declared member alignment changes the generated code for the worse)
     alignas(sizeof(U) == 8 ? 32 : alignof(U)) U As[KC][LDP];  // As[k][i] = A[i][k]
     alignas(sizeof(U) == 8 ? 32 : alignof(U)) U Bs[KC][LDP];  // Bs[k][j] = B[k][j]
     uint32_t kst[ARGMIN == 2 ? kTile * kTile / 4 : 1];       // improving k per entry (bytes)
@@ -399,6 +400,9 @@ __device__ __forceinline__ void minplus_tile_impl(U *__restrict__ D, int32_t *__
     constexpr int CPT = G::cpt;
     constexpr bool NEXT = ARGMIN != 0;
     constexpr int QCAP = MinplusSmem<U, ARGMIN>::QCAP;
+    // chunks of 32 k (64 for the packed form measured slower: more staging
+    // registers per thread outweigh the halved barriers)
+    constexpr int KCT = KC;
     auto &As = sm.As;
     auto &Bs = sm.Bs;
     auto &kst = sm.kst;
@@ -466,12 +470,12 @@ __device__ __forceinline__ void minplus_tile_impl(U *__restrict__ D, int32_t *__
     const int wq = (t >> 6) * QCAP;     // this wave's queue
     const int wq64 = (t >> 6) * 64;     // this wave's search results
 
-    // ---- k loop: stage KC k's of A and B in LDS, then relax
-    constexpr int APT = KC * kTile / NT;          // A entries staged per thread
-    constexpr int BPT = KC * kTile / NT;          // B entries staged per thread
-    const int a_il = t / (KC / APT), a_kq = (t % (KC / APT)) * APT;
+    // ---- k loop: stage KCT k's of A and B in LDS, then relax
+    constexpr int APT = KCT * kTile / NT;         // A entries staged per thread
+    constexpr int BPT = KCT * kTile / NT;         // B entries staged per thread
+    const int a_il = t / (KCT / APT), a_kq = (t % (KCT / APT)) * APT;
     const int b_kk = t / (kTile / BPT), b_jq = (t % (kTile / BPT)) * BPT;
-    for (int kc = 0; kc < bk; kc += KC) {
+    for (int kc = 0; kc < bk; kc += KCT) {
         if (kc) __syncthreads();
         {   // A: As[kk][il] = D[row0 + il][b0 + kc + kk]
             const bool rv = a_il < rows_valid;
@@ -520,7 +524,7 @@ __device__ __forceinline__ void minplus_tile_impl(U *__restrict__ D, int32_t *__
 
         if constexpr (fast) {
 #pragma unroll 1
-            for (int kk = 0; kk < KC; kk += 2) {
+            for (int kk = 0; kk < KCT; kk += 2) {
                 U a[8], b[CPT], a2[8], b2[CPT];
                 lds_operands<U, NT>(As, Bs, kk, tx, ty, a, b);
                 lds_operands<U, NT>(As, Bs, kk + 1, tx, ty, a2, b2);
@@ -1353,6 +1357,26 @@ __global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256) void batched_kernel(
     }
 }
 
+// Resident grid of a persistent-style kernel: workgroups per CU (the
+// kernel's occupancy, computed once per kernel; a relaxed atomic keeps
+// concurrent first calls from different host threads well defined) times CUs.
+hipError_t resident_grid(const void *kern, int threads, std::atomic<int> &per_cu, int *grid) {
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    int pc = per_cu.load(std::memory_order_relaxed);
+    if (pc <= 0) {
+        int nb = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, threads, 0);
+        if (e != hipSuccess) return e;
+        pc = nb > 0 ? nb : 1;
+        per_cu.store(pc, std::memory_order_relaxed);
+    }
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    *grid = pc * cus;
+    return hipSuccess;
+}
+
 template <typename U>
 hipError_t init_t(const Plan &p) {
     dim3 grid((unsigned)((p.n + 255) / 256), (unsigned)imin64(p.n, 65535));
@@ -1401,24 +1425,15 @@ template <typename U, int ARGMIN, bool VEC>
 hipError_t persistent_t(const Plan &p) {
     constexpr int NT = (ARGMIN == 2) ? 512 : 256;
     auto kern = persistent_kernel<U, ARGMIN, VEC>;
-    static int per_cu = -1;                    // resident workgroups per CU
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    if (per_cu < 0) {
-        int nb = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(kern), NT, 0);
-        if (e != hipSuccess) return e;
-        per_cu = nb > 0 ? nb : 1;
-    }
-    int cus = 0;
-    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    static std::atomic<int> per_cu{0};
+    int resident = 0;
+    hipError_t e = resident_grid(reinterpret_cast<const void *>(kern), NT, per_cu, &resident);
     if (e != hipSuccess) return e;
     const int64_t count = persist_ws_ints(p.rounds, p.nt);
     hipLaunchKernelGGL(zero_ints_kernel, dim3(8), dim3(256), 0, p.stream, p.work->persist, count);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t items = 1 + 2 * (int64_t)p.nt + (int64_t)p.nt * p.nt;
-    const int grid = (int)imin64((int64_t)cus * per_cu, items);
+    const int grid = (int)imin64(resident, items);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), 0, p.stream, (U *)p.dist, p.next, p.n, p.ld, p.rounds, p.nt,
                        p.work->persist, p.work->err, p.timeout_ticks);
     return hipGetLastError();
@@ -1476,18 +1491,11 @@ hipError_t batched_t(const BatchPlan &b) {
                        b.next, b.off, b.nv, b.n_max, b.validate ? 1 : 0, b.err);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     auto kern = batched_team_kernel<U, ARGMIN>;
-    static int per_cu = -1;
-    int dev = 0, cus = 0;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-    if (per_cu < 0) {
-        int nb = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(kern), NT, 0);
-        if (e != hipSuccess) return e;
-        per_cu = nb > 0 ? nb : 1;
-    }
-    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    static std::atomic<int> per_cu{0};
+    int resident = 0;
+    if ((e = resident_grid(reinterpret_cast<const void *>(kern), NT, per_cu, &resident)) != hipSuccess) return e;
     const int64_t tickets = (int64_t)b.batch * team_size(b.n_max, b.team_cap);
-    const int grid = (int)imin64((int64_t)cus * per_cu, tickets);
+    const int grid = (int)imin64(resident, tickets);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), 0, b.stream, (U *)b.dist, b.next, b.off, b.nv, sc + L.perm,
                        sc + L.cum, b.batch, b.n_max, sc + L.ticket, sc + L.ws, L.ws_stride, b.err, b.timeout_ticks);
     return hipGetLastError();
