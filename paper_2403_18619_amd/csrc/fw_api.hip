@@ -219,6 +219,13 @@ fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
         // band maxima for the packed-key phase 3 (two round parities)
         s = grow_ints(&p.work->bmax, &p.work->bmax_ints, 4 * (int64_t)p.nt, "band maxima");
         if (s != FW_OK) return s;
+        if (p.bs == fw::kTile) {
+            // packed operand panels of the direct-copy phase 3 (two parities,
+            // A' and B', 128 rows of 128 nt entries each)
+            s = grow_ints(&p.work->panel, &p.work->panel_ints, 4 * (int64_t)fw::kTile * fw::kTile * p.nt,
+                          "operand panels");
+            if (s != FW_OK) return s;
+        }
     }
     hipError_t e = timed(tm, 0, p.stream, [&] { return fw::launch_init(p); });
     if (e != hipSuccess) return hip_fail(e, "init launch");

@@ -23,6 +23,8 @@ struct DeviceWork {
     int64_t bwd_ints = 0;      // its capacity
     int *bmax = nullptr;       // three-launch schedule: band maxima, 4 nt ints
     int64_t bmax_ints = 0;     // its capacity
+    int *panel = nullptr;      // three-launch, block 128: packed operand panels, 4 x 128 x 128 nt
+    int64_t panel_ints = 0;    // its capacity
     hipStream_t aux = nullptr; // three-launch lookahead: the next round's phases 1-2
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
 };

@@ -291,8 +291,8 @@ __device__ __forceinline__ void load_row4(const U *__restrict__ p, int64_t col, 
 
 // Operands of one k of the current chunk: a[] = A[rows of the patch][k],
 // b[] = B[k][columns of the patch].
-template <typename U, int NT>
-__device__ __forceinline__ void lds_operands(const U (*As)[LDP], const U (*Bs)[LDP], int kk, int tx,
+template <typename U, int NT, int P = LDP>
+__device__ __forceinline__ void lds_operands(const U (*As)[P], const U (*Bs)[P], int kk, int tx,
                                              int ty, U a[8], U b[Geo<NT>::cpt]) {
     using V4 = typename Arith<U>::V4;
     const V4 a0 = *reinterpret_cast<const V4 *>(&As[kk][ty * 4]);
@@ -313,6 +313,16 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+__device__ __forceinline__ int ld_flag(const int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+// Waits until this wave's vector-memory operations (its global stores, a
+// cache invalidate) have completed.  A workgroup barrier alone does not: it
+// orders the waves but lets their stores still be on the way to L2.
+__device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // Successor bookkeeping of the min-plus kernel (template argument ARGMIN):
 //   0  distances only: two adds and one v_min3 per pair of k's; 256 threads,
@@ -394,7 +404,8 @@ template <typename U, int ARGMIN, bool VEC, bool PACKED>
 __device__ __forceinline__ void minplus_tile_impl(U *__restrict__ D, int32_t *__restrict__ NX, int64_t n,
                                                   int64_t ld, int K, int BS, int mode, int64_t row0,
                                                   int64_t col0, MinplusSmem<U, ARGMIN> &sm,
-                                                  int *__restrict__ bmax, int nt) {
+                                                  int *__restrict__ bmax, int nt,
+                                                  uint32_t *__restrict__ panel, int64_t ppitch) {
     constexpr int NT = MinplusSmem<U, ARGMIN>::NT;
     using G = Geo<NT>;
     constexpr int CPT = G::cpt;
@@ -739,6 +750,28 @@ __device__ __forceinline__ void minplus_tile_impl(U *__restrict__ D, int32_t *__
             __syncthreads();
             if (t == 0) bm[(mode == 1 ? 0 : nt) + (int)((mode == 1 ? col0 : row0) / kTile)] = (int)sm.bmax_s;
         }
+        // ... and its packed operand panel for the direct-copy phase 3 (block
+        // size 128; round parity K & 1): a row band tile writes
+        // B'[k][j] = pack_b(D[b0 + k][j], k), a column band tile
+        // A'[k][i] = pack_a(D[i][b0 + k]) (transposed: k-major, like LDS)
+        if (mode != 0 && panel) {
+            uint32_t *const pa = panel + (int64_t)(K & 1) * 2 * kTile * ppitch;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int li = G::row_off(tye, r);
+                if (li >= rows_valid) continue;
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    const int lj = G::col_off(txe, c);
+                    if (lj >= cols_valid) continue;
+                    const uint32_t v = (uint32_t)acc[r][c];
+                    if (mode == 1)
+                        pa[(kTile + li) * ppitch + col0 + lj] = pack_b(v, li);
+                    else
+                        pa[lj * ppitch + row0 + li] = pack_a(v);
+                }
+            }
+        }
     }
 
     // ---- store (rows / columns of the band itself are not part of phase 3)
@@ -763,18 +796,20 @@ __device__ __forceinline__ void minplus_tile_impl(U *__restrict__ D, int32_t *__
                 all = all && cs[e];
             }
             if (NEXT) {
-                // only improved entries change
+                // only improved entries change; with packed keys an unimproved
+                // entry holds its clamped key, not its value, so a four-entry
+                // store needs all four improved
                 bool ch[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) ch[e] = cs[e] && idx[r][4 * g + e] >= 0;
-                if (use_vec && all) {
-                    if (ch[0] || ch[1] || ch[2] || ch[3]) {
-                        typename Arith<U>::V4 w;
-                        w.x = acc[r][4 * g + 0]; w.y = acc[r][4 * g + 1];
-                        w.z = acc[r][4 * g + 2]; w.w = acc[r][4 * g + 3];
-                        *reinterpret_cast<typename Arith<U>::V4 *>(drow + lj) = w;
-                    }
-                } else {
+                const bool any4 = ch[0] || ch[1] || ch[2] || ch[3];
+                const bool all4 = ch[0] && ch[1] && ch[2] && ch[3];
+                if (use_vec && all && (fast ? all4 : any4)) {
+                    typename Arith<U>::V4 w;
+                    w.x = acc[r][4 * g + 0]; w.y = acc[r][4 * g + 1];
+                    w.z = acc[r][4 * g + 2]; w.w = acc[r][4 * g + 3];
+                    *reinterpret_cast<typename Arith<U>::V4 *>(drow + lj) = w;
+                } else if (any4) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
                         if (ch[e]) drow[lj + e] = acc[r][4 * g + e];
@@ -798,31 +833,213 @@ __device__ __forceinline__ void minplus_tile_impl(U *__restrict__ D, int32_t *__
     }
 }
 
+// Phase-3 tile with packed keys in the common case of the three-launch
+// schedule: block size = tile edge, a full band of 128 k's, every row and
+// column of the tile inside the matrix, 16-byte aligned rows and a row pitch
+// of at most 2^22 entries.  Same arithmetic, order and results as
+// minplus_tile_impl<uint32_t, 2, VEC, true>.  The operands come from the
+// packed panels the band tiles wrote, copied from memory straight into a
+// double-buffered LDS area; every global address is a per-tile base (scalar
+// registers) plus a per-thread 32-bit byte offset fixed for the whole tile,
+// there are no bounds or band tests, and a wave none of whose entries
+// improved skips the successor gather and the stores.
+constexpr int64_t kFullTileMaxLd = int64_t(1) << 22;
+
+// LDS of the direct-copy form: two chunk buffers of A' (k-major) and B'.
+struct alignas(16) DirectSmem {
+    uint32_t As[2][KC][kTile];
+    uint32_t Bs[2][KC][kTile];
+};
+
+// Addresses of the thread's 8 x 4 patch in a full tile (512 threads).
+struct FullTileGeo {
+    using G = Geo<512>;
+    static_assert(G::cpt == 4 && G::txn == 32, "one 16-byte group of columns per thread and row");
+    int64_t row0, col0, b0, pitch;   // scalar
+    uint32_t toff;                   // patch origin, bytes from the tile corner
+    int tx, ty;
+    __device__ __forceinline__ FullTileGeo(int64_t ld, int K, int64_t row0_, int64_t col0_) {
+        row0 = __builtin_amdgcn_readfirstlane((int)row0_);
+        col0 = __builtin_amdgcn_readfirstlane((int)col0_);
+        b0 = (int64_t)__builtin_amdgcn_readfirstlane(K) * kTile;
+        pitch = ld * 4;
+        int t = threadIdx.x;
+        asm volatile("" : "+v"(t));
+        tx = t % G::txn;
+        ty = t / G::txn;
+        toff = (uint32_t)(ty * 4) * (uint32_t)pitch + (uint32_t)tx * 16u;
+    }
+    // patch row r = tile row (r / 4) * 64 + 4 ty + r % 4
+    static __device__ __forceinline__ int64_t rpart(int r) { return (int64_t)((r >> 2) * 64 + (r & 3)); }
+};
+
+// C of a full tile, as keys.
+__device__ __forceinline__ void full_tile_load_keys(const uint32_t *__restrict__ D, const FullTileGeo &g,
+                                                    uint32_t acc[8][4]) {
+    const char *const cbase = reinterpret_cast<const char *>(D) + g.row0 * g.pitch + g.col0 * 4;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(cbase + FullTileGeo::rpart(r) * g.pitch + g.toff);
+        acc[r][0] = pack_a(v.x); acc[r][1] = pack_a(v.y);
+        acc[r][2] = pack_a(v.z); acc[r][3] = pack_a(v.w);
+    }
+}
+
+// One chunk of KC k's from LDS into the keys (two k's per step).
+template <int P>
+__device__ __forceinline__ void full_tile_chunk(const uint32_t (*As)[P], const uint32_t (*Bs)[P], int tx, int ty,
+                                                uint32_t acc[8][4]) {
+#pragma unroll 1
+    for (int kk = 0; kk < KC; kk += 2) {
+        uint32_t a[8], b[4], a2[8], b2[4];
+        lds_operands<uint32_t, 512, P>(As, Bs, kk, tx, ty, a, b);
+        lds_operands<uint32_t, 512, P>(As, Bs, kk + 1, tx, ty, a2, b2);
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                acc[r][c] = Arith<uint32_t>::mn(acc[r][c], Arith<uint32_t>::mn(a[r] + b[c], a2[r] + b2[c]));
+    }
+}
+
+// Keys -> results: bit 0 = improved, bits 1..7 = k, bits 8.. = value.  The
+// successor of an improved entry is A's, NX[i][b0 + k] (the column band is
+// not written during phase 3); only improved entries are stored, four at
+// once when all four improved (an unimproved key holds the clamped value).
+__device__ __forceinline__ void full_tile_store_keys(uint32_t *__restrict__ D, int32_t *__restrict__ NX,
+                                                     const FullTileGeo &g, const uint32_t acc[8][4]) {
+    uint32_t any = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) any |= acc[r][c];
+    if (!__builtin_amdgcn_ballot_w64((any & 1u) != 0)) return;   // nothing improved in this wave
+    char *const Db = reinterpret_cast<char *>(D);
+    char *const Nb = reinterpret_cast<char *>(NX);
+    int32_t nxv[8][4];
+    const char *const nabase = Nb + g.row0 * g.pitch + g.b0 * 4;
+    const uint32_t nrow = (uint32_t)(g.ty * 4) * (uint32_t)g.pitch;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const char *const na = nabase + FullTileGeo::rpart(r) * g.pitch;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t key = acc[r][c];
+            nxv[r][c] = -1;
+            if (key & 1u) nxv[r][c] = *reinterpret_cast<const int32_t *>(na + (nrow + ((key >> 1) & 127u) * 4u));
+        }
+    }
+    char *const cbase = Db + g.row0 * g.pitch + g.col0 * 4;
+    char *const nbase = Nb + g.row0 * g.pitch + g.col0 * 4;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        char *const dp = cbase + FullTileGeo::rpart(r) * g.pitch + g.toff;
+        char *const np = nbase + FullTileGeo::rpart(r) * g.pitch + g.toff;
+        const bool i0 = acc[r][0] & 1u, i1 = acc[r][1] & 1u, i2 = acc[r][2] & 1u, i3 = acc[r][3] & 1u;
+        if (i0 && i1 && i2 && i3) {
+            uint4 w;
+            w.x = acc[r][0] >> 8; w.y = acc[r][1] >> 8; w.z = acc[r][2] >> 8; w.w = acc[r][3] >> 8;
+            *reinterpret_cast<uint4 *>(dp) = w;
+        } else {
+            if (i0) reinterpret_cast<uint32_t *>(dp)[0] = acc[r][0] >> 8;
+            if (i1) reinterpret_cast<uint32_t *>(dp)[1] = acc[r][1] >> 8;
+            if (i2) reinterpret_cast<uint32_t *>(dp)[2] = acc[r][2] >> 8;
+            if (i3) reinterpret_cast<uint32_t *>(dp)[3] = acc[r][3] >> 8;
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (acc[r][c] & 1u) reinterpret_cast<int32_t *>(np)[c] = nxv[r][c];
+    }
+}
+
+// Direct-copy form: A' and B' of the round (written by the band tiles, round
+// parity K & 1, row pitch ppitch) go from memory to LDS with
+// global_load_lds, no registers and no VALU work; chunk c + 1 is copied into
+// the other buffer while chunk c is relaxed, one barrier per chunk.
+__device__ __forceinline__ void minplus_tile_direct(uint32_t *__restrict__ D, int32_t *__restrict__ NX,
+                                                    int64_t ld, int K, int64_t row0_, int64_t col0_,
+                                                    const uint32_t *__restrict__ panel, int64_t ppitch,
+                                                    DirectSmem &sm) {
+    const FullTileGeo g(ld, K, row0_, col0_);
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t pb = ppitch * 4;                                 // bytes per panel row
+    const int64_t par = (g.b0 / kTile) & 1;
+    const char *const ap = reinterpret_cast<const char *>(panel + par * 2 * kTile * ppitch) + g.row0 * 4;
+    const char *const bp = reinterpret_cast<const char *>(panel + (par * 2 + 1) * kTile * ppitch) + g.col0 * 4;
+    // one global_load_lds of a wave moves 1 KiB = two panel rows of the tile:
+    // lanes 0-31 the first, lanes 32-63 the second, 16 bytes each, landing at
+    // LDS base + 16 * lane
+    const uint32_t loff = (uint32_t)(lane >> 5) * (uint32_t)pb + (uint32_t)(lane & 31) * 16u;
+    auto copy_chunk = [&](int kc, int buf) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int kr = 2 * wv + 16 * q;                        // rows kr, kr + 1 of the chunk
+            const int64_t go = (int64_t)(kc + kr) * pb;
+            // (the address-space casts: global source, LDS destination)
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(ap + go + loff),
+                                             (__attribute__((address_space(3))) void *)&sm.As[buf][kr][0], 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(bp + go + loff),
+                                             (__attribute__((address_space(3))) void *)&sm.Bs[buf][kr][0], 16, 0, 0);
+        }
+    };
+    copy_chunk(0, 0);
+    uint32_t acc[8][4];
+    full_tile_load_keys(D, g, acc);
+#pragma unroll
+    for (int c = 0; c < kTile / KC; ++c) {
+        wait_vmem();                               // this wave's copies of chunk c
+        __syncthreads();                           // everyone's; and chunk c - 1 is consumed
+        if (c + 1 < kTile / KC) copy_chunk((c + 1) * KC, (c + 1) & 1);
+        full_tile_chunk<kTile>(sm.As[c & 1], sm.Bs[c & 1], g.tx, g.ty, acc);
+    }
+    __syncthreads();                               // LDS free for the caller's next tile
+    full_tile_store_keys(D, NX, g, acc);
+}
+
 // One 128 x 128 tile: packed keys when the round's operand panels allow them
 // (int32 with successors, phase 3), the general form otherwise.
 template <typename U, int ARGMIN, bool VEC>
 __device__ __forceinline__ void minplus_tile(U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld,
                                              int K, int BS, int mode, int64_t row0, int64_t col0,
-                                             MinplusSmem<U, ARGMIN> &sm, int *__restrict__ bmax, int nt) {
+                                             MinplusSmem<U, ARGMIN> &sm, int *__restrict__ bmax, int nt,
+                                             uint32_t *__restrict__ panel = nullptr, int64_t ppitch = 0) {
     if constexpr (ARGMIN == 2 && std::is_same<U, uint32_t>::value) {
         if (mode == 0 && bmax) {
             const int *bm = bmax + (K & 1) * 2 * nt;
             const uint32_t ma = (uint32_t)bm[nt + (int)(row0 / kTile)];   // A = column band tile (I, K)
             const uint32_t mb = (uint32_t)bm[(int)(col0 / kTile)];        // B = row band tile (K, J)
             if (ma < kPackLimit && mb < kPackLimit) {
-                minplus_tile_impl<U, ARGMIN, VEC, true>(D, NX, n, ld, K, BS, mode, row0, col0, sm, bmax, nt);
+                minplus_tile_impl<U, ARGMIN, VEC, true>(D, NX, n, ld, K, BS, mode, row0, col0, sm, bmax, nt,
+                                                        nullptr, 0);
                 return;
             }
         }
     }
-    minplus_tile_impl<U, ARGMIN, VEC, false>(D, NX, n, ld, K, BS, mode, row0, col0, sm, bmax, nt);
+    minplus_tile_impl<U, ARGMIN, VEC, false>(D, NX, n, ld, K, BS, mode, row0, col0, sm, bmax, nt, panel, ppitch);
 }
 
+// LDS of a min-plus launch; int32 with deferred successors also holds the
+// direct-copy buffers (same occupancy: two workgroups per CU either way).
+template <typename U, int ARGMIN> struct KernelSmem {
+    MinplusSmem<U, ARGMIN> mp;
+};
+template <> struct KernelSmem<uint32_t, 2> {
+    union {
+        MinplusSmem<uint32_t, 2> mp;
+        DirectSmem dc;
+    };
+};
+
+// panel (int32, deferred successors, block size 128; else null): the packed
+// operand panels, 2 x 2 x 128 rows of ppitch entries, written by phase 2 and
+// read by phase 3's direct-copy tiles.
 template <typename U, int ARGMIN, int PHASE, bool VEC>
 __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves_standalone)) void minplus_kernel(
         U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int K, int BS, int nt,
-        int *__restrict__ bmax, int part) {
-    __shared__ MinplusSmem<U, ARGMIN> sm;
+        int *__restrict__ bmax, int part, uint32_t *__restrict__ panel, int64_t ppitch) {
+    __shared__ KernelSmem<U, ARGMIN> ks;
+    auto &sm = ks.mp;
     const int64_t b0 = (int64_t)K * BS;
     const int64_t b1 = b0 + imin64((int64_t)BS, n - b0);
     int mode;
@@ -853,7 +1070,17 @@ __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves_s
     }
     int64_t row0, col0;
     if (!band_tile(mode, idx, n, b0, b1, nt, row0, col0)) return;
-    minplus_tile<U, ARGMIN, VEC>(D, NX, n, ld, K, BS, mode, row0, col0, sm, bmax, nt);
+    if constexpr (PHASE == 3 && ARGMIN == 2 && VEC && std::is_same<U, uint32_t>::value) {
+        if (panel && BS == kTile && b1 - b0 == kTile && row0 + kTile <= n && col0 + kTile <= n &&
+            ld <= kFullTileMaxLd) {
+            const int *bm = bmax + (K & 1) * 2 * nt;
+            if ((uint32_t)bm[nt + (int)(row0 / kTile)] < kPackLimit && (uint32_t)bm[(int)(col0 / kTile)] < kPackLimit) {
+                minplus_tile_direct(D, NX, ld, K, row0, col0, panel, ppitch, ks.dc);
+                return;
+            }
+        }
+    }
+    minplus_tile<U, ARGMIN, VEC>(D, NX, n, ld, K, BS, mode, row0, col0, sm, bmax, nt, panel, ppitch);
 }
 
 // ------------------------------------------------------ persistent schedule
@@ -918,16 +1145,6 @@ __global__ void zero_ints_kernel(int *w, int64_t count) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
         w[i] = 0;
 }
-
-__device__ __forceinline__ int ld_flag(const int *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
-__device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
-// Waits until this wave's vector-memory operations (its global stores, a
-// cache invalidate) have completed.  A workgroup barrier alone does not: it
-// orders the waves but lets their stores still be on the way to L2.
-__device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // Publishes everything the workgroup has written: every wave drains its
 // stores into L2, then one thread writes the L2 back (agent-scope release)
@@ -1402,16 +1619,18 @@ template <typename U, int ARGMIN, bool VEC>
 hipError_t minplus_t(const Plan &p, int K, int phase, int part) {
     constexpr int NT = Occ<U, ARGMIN>::threads;
     int *bmax = (ARGMIN == 2 && std::is_same<U, uint32_t>::value) ? p.work->bmax : nullptr;
+    uint32_t *panel = (bmax && p.bs == kTile) ? reinterpret_cast<uint32_t *>(p.work->panel) : nullptr;
+    const int64_t ppitch = (int64_t)p.nt * kTile;
     if (phase == 2) {
         hipLaunchKernelGGL((minplus_kernel<U, ARGMIN, 2, VEC>), dim3((unsigned)p.nt, 2), dim3(NT), 0, p.stream,
-                           (U *)p.dist, p.next, p.n, p.ld, K, p.bs, p.nt, bmax, 0);
+                           (U *)p.dist, p.next, p.n, p.ld, K, p.bs, p.nt, bmax, 0, panel, ppitch);
     } else if (part == 1) {
         hipLaunchKernelGGL((minplus_kernel<U, ARGMIN, 3, VEC>), dim3((unsigned)(2 * p.nt)), dim3(NT), 0, p.stream,
-                           (U *)p.dist, p.next, p.n, p.ld, K, p.bs, p.nt, bmax, 1);
+                           (U *)p.dist, p.next, p.n, p.ld, K, p.bs, p.nt, bmax, 1, panel, ppitch);
     } else {
         const int64_t tiles = (int64_t)p.nt * p.nt;
         hipLaunchKernelGGL((minplus_kernel<U, ARGMIN, 3, VEC>), dim3((unsigned)(8 * ((tiles + 7) / 8))), dim3(NT),
-                           0, p.stream, (U *)p.dist, p.next, p.n, p.ld, K, p.bs, p.nt, bmax, part);
+                           0, p.stream, (U *)p.dist, p.next, p.n, p.ld, K, p.bs, p.nt, bmax, part, panel, ppitch);
     }
     return hipGetLastError();
 }
