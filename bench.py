@@ -11,7 +11,8 @@ relaxation).
 
 Prints one JSON line.  Besides the driver's fields it carries
   roofline     : the phase-3 (min-plus) kernel, timed live with HIP events on
-                 the solver's stream, against the MI355X VALU lane-op peak;
+                 the solver's stream, against the MI355X VALU lane-op peak
+                 (two operations per relaxation);
   cpu_baseline : the CPU oracle (plain triple loop) timed on this host on a
                  bounded sample of the same recipe;
   batched      : 4096 graphs, n ~ U{16..256}, edge prob 0.3, float32
@@ -33,14 +34,15 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 64 VALU lanes x 2.4 GHz peak engine clock
-VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
-# fewest VALU lane-ops one min-plus relaxation needs on CDNA4: one 32-bit add
-# plus half of a three-input min (v_min3 folds two candidates into the running
-# minimum); float64 has no three-input min: one v_add_f64 and one v_min_f64,
-# each at the full lane rate (MI355X: 78.6 TFLOP/s FP64 vector = 2 x 39.3 T
-# lane-FMAs/s)
-OPS_PER_RELAX = {"i32": 1.5, "f32": 1.5, "f64": 2.0}
+# MI355X VALU lane-op peak: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz for 32-bit
+# operations (the rate behind the published 157.3 TFLOP/s FP32 vector figure,
+# one FMA = one lane-op = two flops); 64-bit operations at half that (78.6
+# TFLOP/s FP64 vector).
+VALU_PEAK_LANE_OPS = {"i32": 256 * 4 * 32 * 2.4e9, "f32": 256 * 4 * 32 * 2.4e9, "f64": 256 * 4 * 16 * 2.4e9}
+# algorithmic operations per relaxation: one add and one minimum (the paper's
+# two operations per inner iteration); the successor choice rides in the
+# packed keys (int32) or in the chunk-end search and adds none per relaxation
+OPS_PER_RELAX = {"i32": 2.0, "f32": 2.0, "f64": 2.0}
 
 
 def log(msg):
@@ -303,8 +305,9 @@ def main():
     ops = OPS_PER_RELAX[args.dtype]
     achieved = ops * relax_per_launch / avg_s
     traffic = load_traffic(f"{args.dtype}_n{n}_bs{bs}_{'next' if NX is not None else 'dist'}")
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
-                "unit": "Top/s", "frac": achieved / VALU_PEAK_LANE_OPS, "traffic": traffic,
+    peak = VALU_PEAK_LANE_OPS[args.dtype]
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                "unit": "Top/s", "frac": achieved / peak, "traffic": traffic,
                 "kernel": kind, "avg_launch_ms": avg_s * 1e3, "launches_per_step": k_launches / args.steps,
                 "ops_per_relaxation": ops}
     phase_ms = {k: (v[0] / args.steps) for k, v in ph.items() if v[1]}

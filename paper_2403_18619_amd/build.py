@@ -9,6 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 SO = os.path.join(PKG, "libfwgpu.so")
+CEILING = os.path.join(PKG, "ceiling")
 SOURCES = ["fw_kernels.hip", "fw_backward.hip", "fw_api.hip"]
 
 HIPCC_FLAGS = [
@@ -41,6 +42,11 @@ def build(verbose: bool = False, extra=()) -> str:
     os.replace(tmp, SO)
     for o in objs:
         os.remove(o)
+    # the measured-ceiling program (standalone, not part of the library)
+    cmd = [hipcc(), *HIPCC_FLAGS, *extra, os.path.join(CSRC, "ceiling.hip"), "-o", CEILING]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
     return SO
 
 
