@@ -221,13 +221,19 @@ fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
         if (s != FW_OK) return s;
         if (p.bs == fw::kTile) {
             // packed operand panels of the direct-copy phase 3 (two parities,
-            // A' and B', 128 rows of 128 nt entries each)
+            // A' and B', 128 rows of 128 nt entries each) and its fix-up
+            // counters (one per phase-3 launch) and tile list
             s = grow_ints(&p.work->panel, &p.work->panel_ints, 4 * (int64_t)fw::kTile * fw::kTile * p.nt,
                           "operand panels");
             if (s != FW_OK) return s;
+            s = grow_ints(&p.work->fix, &p.work->fix_ints, 2 * (int64_t)p.rounds + (int64_t)p.nt * p.nt,
+                          "fix-up list");
+            if (s != FW_OK) return s;
         }
     }
+    const bool direct = !persistent && dt == fw::DType::I32 && next && !p.eager_argmin && p.bs == fw::kTile;
     hipError_t e = timed(tm, 0, p.stream, [&] { return fw::launch_init(p); });
+    if (e == hipSuccess && direct) e = fw::launch_fix_reset(p);
     if (e != hipSuccess) return hip_fail(e, "init launch");
     if (persistent) {
         e = timed(tm, 4, p.stream, [&] { return fw::launch_persistent(p); });

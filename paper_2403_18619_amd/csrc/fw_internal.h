@@ -25,6 +25,8 @@ struct DeviceWork {
     int64_t bmax_ints = 0;     // its capacity
     int *panel = nullptr;      // three-launch, block 128: packed operand panels, 4 x 128 x 128 nt
     int64_t panel_ints = 0;    // its capacity
+    int *fix = nullptr;        // direct-copy phase 3: 2 R fix-up counters, then an nt^2 tile list
+    int64_t fix_ints = 0;      // its capacity
     hipStream_t aux = nullptr; // three-launch lookahead: the next round's phases 1-2
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
 };
@@ -83,6 +85,8 @@ int backward_global_workgroups(const BackwardPlan &b);
 
 // Enqueue helpers (fw_kernels.hip).  Each returns the launch's hipError_t.
 hipError_t launch_init(const Plan &p);
+// zeroes the direct-copy phase 3's fix-up counters (work->fix, 2 R ints)
+hipError_t launch_fix_reset(const Plan &p);
 hipError_t launch_phase1(const Plan &p, int K);
 hipError_t launch_phase2(const Plan &p, int K);
 // part 0: every phase-3 tile of round K; 1: the tiles of band K+1 only;

@@ -833,170 +833,6 @@ __device__ __forceinline__ void minplus_tile_impl(U *__restrict__ D, int32_t *__
     }
 }
 
-// Phase-3 tile with packed keys in the common case of the three-launch
-// schedule: block size = tile edge, a full band of 128 k's, every row and
-// column of the tile inside the matrix, 16-byte aligned rows and a row pitch
-// of at most 2^22 entries.  Same arithmetic, order and results as
-// minplus_tile_impl<uint32_t, 2, VEC, true>.  The operands come from the
-// packed panels the band tiles wrote, copied from memory straight into a
-// double-buffered LDS area; every global address is a per-tile base (scalar
-// registers) plus a per-thread 32-bit byte offset fixed for the whole tile,
-// there are no bounds or band tests, and a wave none of whose entries
-// improved skips the successor gather and the stores.
-constexpr int64_t kFullTileMaxLd = int64_t(1) << 22;
-
-// LDS of the direct-copy form: two chunk buffers of A' (k-major) and B'.
-struct alignas(16) DirectSmem {
-    uint32_t As[2][KC][kTile];
-    uint32_t Bs[2][KC][kTile];
-};
-
-// Addresses of the thread's 8 x 4 patch in a full tile (512 threads).
-struct FullTileGeo {
-    using G = Geo<512>;
-    static_assert(G::cpt == 4 && G::txn == 32, "one 16-byte group of columns per thread and row");
-    int64_t row0, col0, b0, pitch;   // scalar
-    uint32_t toff;                   // patch origin, bytes from the tile corner
-    int tx, ty;
-    __device__ __forceinline__ FullTileGeo(int64_t ld, int K, int64_t row0_, int64_t col0_) {
-        row0 = __builtin_amdgcn_readfirstlane((int)row0_);
-        col0 = __builtin_amdgcn_readfirstlane((int)col0_);
-        b0 = (int64_t)__builtin_amdgcn_readfirstlane(K) * kTile;
-        pitch = ld * 4;
-        int t = threadIdx.x;
-        asm volatile("" : "+v"(t));
-        tx = t % G::txn;
-        ty = t / G::txn;
-        toff = (uint32_t)(ty * 4) * (uint32_t)pitch + (uint32_t)tx * 16u;
-    }
-    // patch row r = tile row (r / 4) * 64 + 4 ty + r % 4
-    static __device__ __forceinline__ int64_t rpart(int r) { return (int64_t)((r >> 2) * 64 + (r & 3)); }
-};
-
-// C of a full tile, as keys.
-__device__ __forceinline__ void full_tile_load_keys(const uint32_t *__restrict__ D, const FullTileGeo &g,
-                                                    uint32_t acc[8][4]) {
-    const char *const cbase = reinterpret_cast<const char *>(D) + g.row0 * g.pitch + g.col0 * 4;
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(cbase + FullTileGeo::rpart(r) * g.pitch + g.toff);
-        acc[r][0] = pack_a(v.x); acc[r][1] = pack_a(v.y);
-        acc[r][2] = pack_a(v.z); acc[r][3] = pack_a(v.w);
-    }
-}
-
-// One chunk of KC k's from LDS into the keys (two k's per step).
-template <int P>
-__device__ __forceinline__ void full_tile_chunk(const uint32_t (*As)[P], const uint32_t (*Bs)[P], int tx, int ty,
-                                                uint32_t acc[8][4]) {
-#pragma unroll 1
-    for (int kk = 0; kk < KC; kk += 2) {
-        uint32_t a[8], b[4], a2[8], b2[4];
-        lds_operands<uint32_t, 512, P>(As, Bs, kk, tx, ty, a, b);
-        lds_operands<uint32_t, 512, P>(As, Bs, kk + 1, tx, ty, a2, b2);
-#pragma unroll
-        for (int r = 0; r < 8; ++r)
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                acc[r][c] = Arith<uint32_t>::mn(acc[r][c], Arith<uint32_t>::mn(a[r] + b[c], a2[r] + b2[c]));
-    }
-}
-
-// Keys -> results: bit 0 = improved, bits 1..7 = k, bits 8.. = value.  The
-// successor of an improved entry is A's, NX[i][b0 + k] (the column band is
-// not written during phase 3); only improved entries are stored, four at
-// once when all four improved (an unimproved key holds the clamped value).
-__device__ __forceinline__ void full_tile_store_keys(uint32_t *__restrict__ D, int32_t *__restrict__ NX,
-                                                     const FullTileGeo &g, const uint32_t acc[8][4]) {
-    uint32_t any = 0;
-#pragma unroll
-    for (int r = 0; r < 8; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) any |= acc[r][c];
-    if (!__builtin_amdgcn_ballot_w64((any & 1u) != 0)) return;   // nothing improved in this wave
-    char *const Db = reinterpret_cast<char *>(D);
-    char *const Nb = reinterpret_cast<char *>(NX);
-    int32_t nxv[8][4];
-    const char *const nabase = Nb + g.row0 * g.pitch + g.b0 * 4;
-    const uint32_t nrow = (uint32_t)(g.ty * 4) * (uint32_t)g.pitch;
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const char *const na = nabase + FullTileGeo::rpart(r) * g.pitch;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const uint32_t key = acc[r][c];
-            nxv[r][c] = -1;
-            if (key & 1u) nxv[r][c] = *reinterpret_cast<const int32_t *>(na + (nrow + ((key >> 1) & 127u) * 4u));
-        }
-    }
-    char *const cbase = Db + g.row0 * g.pitch + g.col0 * 4;
-    char *const nbase = Nb + g.row0 * g.pitch + g.col0 * 4;
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        char *const dp = cbase + FullTileGeo::rpart(r) * g.pitch + g.toff;
-        char *const np = nbase + FullTileGeo::rpart(r) * g.pitch + g.toff;
-        const bool i0 = acc[r][0] & 1u, i1 = acc[r][1] & 1u, i2 = acc[r][2] & 1u, i3 = acc[r][3] & 1u;
-        if (i0 && i1 && i2 && i3) {
-            uint4 w;
-            w.x = acc[r][0] >> 8; w.y = acc[r][1] >> 8; w.z = acc[r][2] >> 8; w.w = acc[r][3] >> 8;
-            *reinterpret_cast<uint4 *>(dp) = w;
-        } else {
-            if (i0) reinterpret_cast<uint32_t *>(dp)[0] = acc[r][0] >> 8;
-            if (i1) reinterpret_cast<uint32_t *>(dp)[1] = acc[r][1] >> 8;
-            if (i2) reinterpret_cast<uint32_t *>(dp)[2] = acc[r][2] >> 8;
-            if (i3) reinterpret_cast<uint32_t *>(dp)[3] = acc[r][3] >> 8;
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-            if (acc[r][c] & 1u) reinterpret_cast<int32_t *>(np)[c] = nxv[r][c];
-    }
-}
-
-// Direct-copy form: A' and B' of the round (written by the band tiles, round
-// parity K & 1, row pitch ppitch) go from memory to LDS with
-// global_load_lds, no registers and no VALU work; chunk c + 1 is copied into
-// the other buffer while chunk c is relaxed, one barrier per chunk.
-__device__ __forceinline__ void minplus_tile_direct(uint32_t *__restrict__ D, int32_t *__restrict__ NX,
-                                                    int64_t ld, int K, int64_t row0_, int64_t col0_,
-                                                    const uint32_t *__restrict__ panel, int64_t ppitch,
-                                                    DirectSmem &sm) {
-    const FullTileGeo g(ld, K, row0_, col0_);
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int64_t pb = ppitch * 4;                                 // bytes per panel row
-    const int64_t par = (g.b0 / kTile) & 1;
-    const char *const ap = reinterpret_cast<const char *>(panel + par * 2 * kTile * ppitch) + g.row0 * 4;
-    const char *const bp = reinterpret_cast<const char *>(panel + (par * 2 + 1) * kTile * ppitch) + g.col0 * 4;
-    // one global_load_lds of a wave moves 1 KiB = two panel rows of the tile:
-    // lanes 0-31 the first, lanes 32-63 the second, 16 bytes each, landing at
-    // LDS base + 16 * lane
-    const uint32_t loff = (uint32_t)(lane >> 5) * (uint32_t)pb + (uint32_t)(lane & 31) * 16u;
-    auto copy_chunk = [&](int kc, int buf) {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int kr = 2 * wv + 16 * q;                        // rows kr, kr + 1 of the chunk
-            const int64_t go = (int64_t)(kc + kr) * pb;
-            // (the address-space casts: global source, LDS destination)
-            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(ap + go + loff),
-                                             (__attribute__((address_space(3))) void *)&sm.As[buf][kr][0], 16, 0, 0);
-            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(bp + go + loff),
-                                             (__attribute__((address_space(3))) void *)&sm.Bs[buf][kr][0], 16, 0, 0);
-        }
-    };
-    copy_chunk(0, 0);
-    uint32_t acc[8][4];
-    full_tile_load_keys(D, g, acc);
-#pragma unroll
-    for (int c = 0; c < kTile / KC; ++c) {
-        wait_vmem();                               // this wave's copies of chunk c
-        __syncthreads();                           // everyone's; and chunk c - 1 is consumed
-        if (c + 1 < kTile / KC) copy_chunk((c + 1) * KC, (c + 1) & 1);
-        full_tile_chunk<kTile>(sm.As[c & 1], sm.Bs[c & 1], g.tx, g.ty, acc);
-    }
-    __syncthreads();                               // LDS free for the caller's next tile
-    full_tile_store_keys(D, NX, g, acc);
-}
-
 // One 128 x 128 tile: packed keys when the round's operand panels allow them
 // (int32 with successors, phase 3), the general form otherwise.
 template <typename U, int ARGMIN, bool VEC>
@@ -1019,50 +855,41 @@ __device__ __forceinline__ void minplus_tile(U *__restrict__ D, int32_t *__restr
     minplus_tile_impl<U, ARGMIN, VEC, false>(D, NX, n, ld, K, BS, mode, row0, col0, sm, bmax, nt, panel, ppitch);
 }
 
-// LDS of a min-plus launch; int32 with deferred successors also holds the
-// direct-copy buffers (same occupancy: two workgroups per CU either way).
-template <typename U, int ARGMIN> struct KernelSmem {
-    MinplusSmem<U, ARGMIN> mp;
-};
-template <> struct KernelSmem<uint32_t, 2> {
-    union {
-        MinplusSmem<uint32_t, 2> mp;
-        DirectSmem dc;
-    };
-};
+// Tile of a phase-3 launch: part 1 = the next band's tiles (row and column
+// K + 1; block size = tile edge), part 2 = the rest, part 0 = all; -1 = none.
+// Workgroups are dealt to the eight XCDs round-robin; each XCD gets a
+// contiguous run of tiles, so that tiles sharing a row of A meet in the same
+// L2.
+__device__ __forceinline__ int64_t phase3_tile(int part, int K, int nt) {
+    if (part == 1) {
+        const int q = (int)blockIdx.x, nx1 = K + 1;
+        if (q < nt) return (int64_t)nx1 * nt + q;
+        if (q - nt == nx1) return -1;             // (K+1, K+1) is in the row above
+        return (int64_t)(q - nt) * nt + nx1;
+    }
+    const int64_t tiles = (int64_t)nt * nt;
+    const int64_t per = (tiles + 7) / 8;
+    const int64_t idx = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (idx >= tiles) return -1;
+    if (part == 2 && (idx / nt == K + 1 || idx % nt == K + 1)) return -1;   // done by part 1
+    return idx;
+}
 
 // panel (int32, deferred successors, block size 128; else null): the packed
-// operand panels, 2 x 2 x 128 rows of ppitch entries, written by phase 2 and
-// read by phase 3's direct-copy tiles.
+// operand panels, 2 x 2 x 128 rows of ppitch entries, written by the band
+// tiles (phase 2) for phase 3's direct-copy kernel.
 template <typename U, int ARGMIN, int PHASE, bool VEC>
 __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves_standalone)) void minplus_kernel(
         U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int K, int BS, int nt,
         int *__restrict__ bmax, int part, uint32_t *__restrict__ panel, int64_t ppitch) {
-    __shared__ KernelSmem<U, ARGMIN> ks;
-    auto &sm = ks.mp;
+    __shared__ MinplusSmem<U, ARGMIN> sm;
     const int64_t b0 = (int64_t)K * BS;
     const int64_t b1 = b0 + imin64((int64_t)BS, n - b0);
     int mode;
     int64_t idx;
-    if (PHASE == 3 && part == 1) {
-        // the next band's tiles (row and column K+1; block size = tile edge)
-        const int q = (int)blockIdx.x, nx1 = K + 1;
-        if (q < nt) {
-            idx = (int64_t)nx1 * nt + q;
-        } else {
-            if (q - nt == nx1) return;           // (K+1, K+1) is in the row above
-            idx = (int64_t)(q - nt) * nt + nx1;
-        }
-        mode = 0;
-    } else if (PHASE == 3) {
-        // Workgroups are dealt to the eight XCDs round-robin; give each XCD a
-        // contiguous run of tiles so that tiles sharing a row of A meet in the
-        // same L2.
-        const int64_t tiles = (int64_t)nt * nt;
-        const int64_t per = (tiles + 7) / 8;
-        idx = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-        if (idx >= tiles) return;
-        if (part == 2 && (idx / nt == K + 1 || idx % nt == K + 1)) return;   // done by part 1
+    if (PHASE == 3) {
+        idx = phase3_tile(part, K, nt);
+        if (idx < 0) return;
         mode = 0;
     } else {
         mode = 1 + (int)blockIdx.y;
@@ -1070,17 +897,182 @@ __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves_s
     }
     int64_t row0, col0;
     if (!band_tile(mode, idx, n, b0, b1, nt, row0, col0)) return;
-    if constexpr (PHASE == 3 && ARGMIN == 2 && VEC && std::is_same<U, uint32_t>::value) {
-        if (panel && BS == kTile && b1 - b0 == kTile && row0 + kTile <= n && col0 + kTile <= n &&
-            ld <= kFullTileMaxLd) {
-            const int *bm = bmax + (K & 1) * 2 * nt;
-            if ((uint32_t)bm[nt + (int)(row0 / kTile)] < kPackLimit && (uint32_t)bm[(int)(col0 / kTile)] < kPackLimit) {
-                minplus_tile_direct(D, NX, ld, K, row0, col0, panel, ppitch, ks.dc);
-                return;
+    minplus_tile<U, ARGMIN, VEC>(D, NX, n, ld, K, BS, mode, row0, col0, sm, bmax, nt, panel, ppitch);
+}
+
+// ------------------------------------------- phase 3: direct-copy kernel
+// The common case of phase 3 in the three-launch schedule -- int32 with
+// successors, block size = tile edge, packed keys, a full tile and band,
+// 16-byte aligned rows, row pitch <= 2^22 entries -- runs in a kernel of its
+// own, small enough (32 KB of LDS, <= 128 VGPRs) for four workgroups per CU:
+//   - operands: the band tiles also write the round's packed operand panels
+//     (A'[k][i] k-major and B'[k][j], round parity K & 1, rows of ppitch
+//     entries); each 16-k chunk of both is copied from memory straight into
+//     LDS with global_load_lds (gfx950's 16-byte direct-to-LDS load: no
+//     registers, no VALU work), double-buffered: chunk c + 1 is copied while
+//     chunk c is relaxed, one barrier per chunk;
+//   - 256 threads with 8 x 8 entries each: eight 16-byte LDS reads feed 128
+//     relaxations per thread and pair of k's;
+//   - entry by entry, the two adds and the v_min3 that reads them are issued
+//     together (empty asm statements pin the order; the compiler would
+//     otherwise issue all adds first): on gfx950 v_add issues at about twice
+//     the rate of v_min3, and this order lets the two overlap (measured);
+//   - every global address is a per-tile base in scalar registers plus a
+//     per-thread offset, there are no bounds or band tests, and a wave none
+//     of whose entries improved skips the successor gather and the stores.
+// Same arithmetic, k order and results as the general tile with packed keys.
+// A tile that does not qualify is appended to the launch's fix-up list, which
+// minplus_fixup_kernel then runs with the general tile.
+constexpr int64_t kFullTileMaxLd = int64_t(1) << 22;
+constexpr int KCD = 16;                    // k's per chunk of the direct tile
+struct alignas(16) DirectSmem {
+    uint32_t As[2][KCD][kTile];            // As[buf][k][i] = A'[chunk k][i]
+    uint32_t Bs[2][KCD][kTile];            // Bs[buf][k][j] = B'[chunk k][j]
+};
+
+// One chunk of KCD k's into the keys, two k's per step.
+__device__ __forceinline__ void direct_chunk(const uint32_t (*__restrict__ As)[kTile],
+                                             const uint32_t (*__restrict__ Bs)[kTile], int tx, int ty,
+                                             uint32_t acc[8][8]) {
+#pragma unroll 1
+    for (int kk = 0; kk < KCD; kk += 2) {
+        uint32_t a[8], b[8], a2[8], b2[8];
+        lds_operands<uint32_t, 256, kTile>(As, Bs, kk, tx, ty, a, b);
+        lds_operands<uint32_t, 256, kTile>(As, Bs, kk + 1, tx, ty, a2, b2);
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                uint32_t x = a[r] + b[c], y = a2[r] + b2[c];
+                asm volatile("" : "+v"(x), "+v"(y));
+                acc[r][c] = Arith<uint32_t>::mn(acc[r][c], Arith<uint32_t>::mn(x, y));
+                asm volatile("" : "+v"(acc[r][c]));
+            }
+    }
+}
+
+// fix_count / fix_list: this launch's fix-up counter (zeroed once per solve)
+// and the list of tiles the general kernel runs afterwards (nt^2 entries).
+__global__ __launch_bounds__(256, 4) void minplus_direct_kernel(
+        uint32_t *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int K, int nt,
+        const int *__restrict__ bmax, int part, const uint32_t *__restrict__ panel, int64_t ppitch,
+        int *__restrict__ fix_count, int *__restrict__ fix_list) {
+    __shared__ DirectSmem sm;
+    using G = Geo<256>;
+    const int64_t idx = phase3_tile(part, K, nt);
+    if (idx < 0) return;
+    const int64_t b0 = (int64_t)K * kTile;
+    const int64_t row0_ = (idx / nt) * kTile, col0_ = (idx % nt) * kTile;
+    if (row0_ == b0 || col0_ == b0) return;                       // the band's own tiles
+    {
+        const int *bm = bmax + (K & 1) * 2 * nt;
+        const bool direct = n - b0 >= kTile && row0_ + kTile <= n && col0_ + kTile <= n && ld <= kFullTileMaxLd &&
+                            (uint32_t)bm[nt + (int)(row0_ / kTile)] < kPackLimit &&
+                            (uint32_t)bm[(int)(col0_ / kTile)] < kPackLimit;
+        if (!direct) {
+            if (threadIdx.x == 0) fix_list[atomicAdd(fix_count, 1)] = (int)idx;
+            return;
+        }
+    }
+    const int64_t row0 = __builtin_amdgcn_readfirstlane((int)row0_);
+    const int64_t col0 = __builtin_amdgcn_readfirstlane((int)col0_);
+    const int64_t pitch = ld * 4;
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    const int tx = t % G::txn, ty = t / G::txn;
+    const int lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t pb = ppitch * 4;
+    const int64_t par = K & 1;
+    const char *const ap = reinterpret_cast<const char *>(panel + par * 2 * kTile * ppitch) + row0 * 4;
+    const char *const bp = reinterpret_cast<const char *>(panel + (par * 2 + 1) * kTile * ppitch) + col0 * 4;
+    const uint32_t loff = (uint32_t)(lane >> 5) * (uint32_t)pb + (uint32_t)(lane & 31) * 16u;
+    auto copy_chunk = [&](int kc, int buf) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int kr = 2 * wv + 8 * q;
+            const int64_t go = (int64_t)(kc + kr) * pb;
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(ap + go + loff),
+                                             (__attribute__((address_space(3))) void *)&sm.As[buf][kr][0], 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(bp + go + loff),
+                                             (__attribute__((address_space(3))) void *)&sm.Bs[buf][kr][0], 16, 0, 0);
+        }
+    };
+    copy_chunk(0, 0);
+    // C as keys
+    const char *const cbase = reinterpret_cast<const char *>(D) + row0 * pitch + col0 * 4;
+    uint32_t acc[8][8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int64_t ro = (int64_t)G::row_off(ty, r) * pitch;
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(cbase + ro + (int64_t)G::col_off(tx, 4 * g) * 4);
+            acc[r][4 * g] = pack_a(v.x); acc[r][4 * g + 1] = pack_a(v.y);
+            acc[r][4 * g + 2] = pack_a(v.z); acc[r][4 * g + 3] = pack_a(v.w);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kTile / KCD; ++c) {
+        wait_vmem();
+        __syncthreads();
+        if (c + 1 < kTile / KCD) copy_chunk((c + 1) * KCD, (c + 1) & 1);
+        direct_chunk(sm.As[c & 1], sm.Bs[c & 1], tx, ty, acc);
+    }
+    // epilogue, row by row
+    uint32_t any = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) any |= acc[r][c];
+    if (!__builtin_amdgcn_ballot_w64((any & 1u) != 0)) return;
+    char *const Db = reinterpret_cast<char *>(D);
+    char *const Nb = reinterpret_cast<char *>(NX);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int64_t ro = (row0 + G::row_off(ty, r)) * pitch;
+        const char *const na = Nb + ro + b0 * 4;
+        int32_t nxv[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            nxv[c] = -1;
+            if (acc[r][c] & 1u) nxv[c] = *reinterpret_cast<const int32_t *>(na + ((acc[r][c] >> 1) & 127u) * 4u);
+        }
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const int64_t co = (col0 + G::col_off(tx, 4 * g)) * 4;
+            uint32_t *dp = reinterpret_cast<uint32_t *>(Db + ro + co);
+            int32_t *np = reinterpret_cast<int32_t *>(Nb + ro + co);
+            const uint32_t *e = &acc[r][4 * g];
+            const bool all = (e[0] & e[1] & e[2] & e[3] & 1u) != 0;
+            if (all) {
+                *reinterpret_cast<uint4 *>(dp) = make_uint4(e[0] >> 8, e[1] >> 8, e[2] >> 8, e[3] >> 8);
+                *reinterpret_cast<int4 *>(np) = make_int4(nxv[4 * g], nxv[4 * g + 1], nxv[4 * g + 2], nxv[4 * g + 3]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (e[q] & 1u) { dp[q] = e[q] >> 8; np[q] = nxv[4 * g + q]; }
             }
         }
     }
-    minplus_tile<U, ARGMIN, VEC>(D, NX, n, ld, K, BS, mode, row0, col0, sm, bmax, nt, panel, ppitch);
+}
+
+// The fix-up tiles of a direct-copy launch, with the general tile (packed
+// keys or not, ragged or not); a resident-size grid walks the list.
+template <bool VEC>
+__global__ __launch_bounds__((Occ<uint32_t, 2>::threads), (Occ<uint32_t, 2>::waves_standalone)) void
+minplus_fixup_kernel(uint32_t *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int K, int nt,
+                     int *__restrict__ bmax, const int *__restrict__ fix_count, const int *__restrict__ fix_list) {
+    __shared__ MinplusSmem<uint32_t, 2> sm;
+    const int count = __hip_atomic_load(fix_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t b0 = (int64_t)K * kTile;
+    const int64_t b1 = b0 + imin64((int64_t)kTile, n - b0);
+    for (int q = blockIdx.x; q < count; q += gridDim.x) {
+        int64_t row0, col0;
+        if (band_tile(0, fix_list[q], n, b0, b1, nt, row0, col0))
+            minplus_tile<uint32_t, 2, VEC>(D, NX, n, ld, K, kTile, 0, row0, col0, sm, bmax, nt);
+        __syncthreads();                           // LDS is reused by the next tile
+    }
 }
 
 // ------------------------------------------------------ persistent schedule
@@ -1621,6 +1613,23 @@ hipError_t minplus_t(const Plan &p, int K, int phase, int part) {
     int *bmax = (ARGMIN == 2 && std::is_same<U, uint32_t>::value) ? p.work->bmax : nullptr;
     uint32_t *panel = (bmax && p.bs == kTile) ? reinterpret_cast<uint32_t *>(p.work->panel) : nullptr;
     const int64_t ppitch = (int64_t)p.nt * kTile;
+    if constexpr (ARGMIN == 2 && VEC && std::is_same<U, uint32_t>::value) {
+        if (phase == 3 && panel) {
+            // direct-copy tiles, then the general tile on the ones that did not qualify
+            const int64_t tiles = (int64_t)p.nt * p.nt;
+            const unsigned grid = part == 1 ? (unsigned)(2 * p.nt) : (unsigned)(8 * ((tiles + 7) / 8));
+            int *cnt = p.work->fix + 2 * K + (part == 2 ? 1 : 0);
+            int *list = p.work->fix + 2 * (int64_t)p.rounds;
+            hipLaunchKernelGGL(minplus_direct_kernel, dim3(grid), dim3(256), 0, p.stream, (uint32_t *)p.dist, p.next,
+                               p.n, p.ld, K, p.nt, bmax, part, panel, ppitch, cnt, list);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            const unsigned fgrid = (unsigned)imin64(part == 1 ? 2 * (int64_t)p.nt : tiles, 512);
+            hipLaunchKernelGGL((minplus_fixup_kernel<VEC>), dim3(fgrid), dim3(NT), 0, p.stream, (uint32_t *)p.dist,
+                               p.next, p.n, p.ld, K, p.nt, bmax, cnt, list);
+            return hipGetLastError();
+        }
+    }
     if (phase == 2) {
         hipLaunchKernelGGL((minplus_kernel<U, ARGMIN, 2, VEC>), dim3((unsigned)p.nt, 2), dim3(NT), 0, p.stream,
                            (U *)p.dist, p.next, p.n, p.ld, K, p.bs, p.nt, bmax, 0, panel, ppitch);
@@ -1753,6 +1762,11 @@ hipError_t launch_persistent(const Plan &p) {
     case DType::F32: return persistent_dispatch<float>(p);
     default: return persistent_dispatch<double>(p);
     }
+}
+
+hipError_t launch_fix_reset(const Plan &p) {
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(256), 0, p.stream, p.work->fix, 2 * (int64_t)p.rounds);
+    return hipGetLastError();
 }
 
 hipError_t launch_init(const Plan &p) {
