@@ -109,7 +109,8 @@ typedef struct fw_options {
  * besides the small workspace, an int32 solve with successors in the
  * three-launch schedule keeps 2 x ceil(n/128) band maxima and, at block size
  * 128, the rounds' packed operand panels, 4 x 128 x 128 ceil(n/128) int32
- * (64 MiB at n = 32768); a call that has to grow them allocates, so capture a
+ * (64 MiB at n = 32768), and a phase-3 fix-up list of 2 R + ceil(n/128)^2
+ * int32 (R rounds); a call that has to grow them allocates, so capture a
  * solve in a hipGraph after one uncaptured call of the same or larger n. */
 fw_status fw_solve_i32(int32_t *dist, int32_t *next, int64_t n, int64_t ld, void *stream);
 fw_status fw_solve_f32(float *dist, int32_t *next, int64_t n, int64_t ld, void *stream);
