@@ -986,6 +986,11 @@ __global__ __launch_bounds__(256, 4) void minplus_direct_kernel(
     const int64_t par = K & 1;
     const char *const ap = reinterpret_cast<const char *>(panel + par * 2 * kTile * ppitch) + row0 * 4;
     const char *const bp = reinterpret_cast<const char *>(panel + (par * 2 + 1) * kTile * ppitch) + col0 * 4;
+    // One global_load_lds of a wave moves 1 KiB, two panel rows of the tile:
+    // lanes 0-31 row kr, lanes 32-63 row kr + 1, 16 bytes each, landing at LDS
+    // base + 16 lane (the instruction offset, unused, would apply to both
+    // addresses); the four waves move a 16-row chunk of A' and of B' in two
+    // each.  (The casts name the global source and LDS destination spaces.)
     const uint32_t loff = (uint32_t)(lane >> 5) * (uint32_t)pb + (uint32_t)(lane & 31) * 16u;
     auto copy_chunk = [&](int kc, int buf) {
 #pragma unroll
@@ -999,7 +1004,7 @@ __global__ __launch_bounds__(256, 4) void minplus_direct_kernel(
         }
     };
     copy_chunk(0, 0);
-    // C as keys
+    // C as keys (min(C, S) << 8)
     const char *const cbase = reinterpret_cast<const char *>(D) + row0 * pitch + col0 * 4;
     uint32_t acc[8][8];
 #pragma unroll
@@ -1014,12 +1019,16 @@ __global__ __launch_bounds__(256, 4) void minplus_direct_kernel(
     }
 #pragma unroll
     for (int c = 0; c < kTile / KCD; ++c) {
-        wait_vmem();
-        __syncthreads();
+        wait_vmem();                               // this wave's copies of chunk c (and C)
+        __syncthreads();                           // everyone's; and chunk c - 1 is consumed
         if (c + 1 < kTile / KCD) copy_chunk((c + 1) * KCD, (c + 1) & 1);
         direct_chunk(sm.As[c & 1], sm.Bs[c & 1], tx, ty, acc);
     }
-    // epilogue, row by row
+    // Keys -> results, row by row: bit 0 = improved, bits 1..7 = k, bits 8.. =
+    // value.  The successor of an improved entry is A's, NX[i][b0 + k] (the
+    // column band is not written during phase 3); only improved entries are
+    // stored, four at once only when all four improved (an unimproved key
+    // holds min(C, S), not C).
     uint32_t any = 0;
 #pragma unroll
     for (int r = 0; r < 8; ++r)
