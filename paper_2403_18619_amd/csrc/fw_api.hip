@@ -215,23 +215,24 @@ fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
         s = persistent_plan(p, (o.flags & FW_FLAG_TEST_TIMEOUT) != 0);
         if (s != FW_OK) return s;
     }
-    if (!persistent && dt == fw::DType::I32 && next && !p.eager_argmin) {
+    const bool packed = !persistent && dt == fw::DType::I32 && next && !p.eager_argmin;
+    if (packed) {
         // band maxima for the packed-key phase 3 (two round parities)
         s = grow_ints(&p.work->bmax, &p.work->bmax_ints, 4 * (int64_t)p.nt, "band maxima");
         if (s != FW_OK) return s;
-        if (p.bs == fw::kTile) {
-            // packed operand panels of the direct-copy phase 3 (two parities,
-            // A' and B', 128 rows of 128 nt entries each) and its fix-up
-            // counters (one per phase-3 launch) and tile list
-            s = grow_ints(&p.work->panel, &p.work->panel_ints, 4 * (int64_t)fw::kTile * fw::kTile * p.nt,
-                          "operand panels");
-            if (s != FW_OK) return s;
-            s = grow_ints(&p.work->fix, &p.work->fix_ints, 2 * (int64_t)p.rounds + (int64_t)p.nt * p.nt,
-                          "fix-up list");
-            if (s != FW_OK) return s;
-        }
     }
-    const bool direct = !persistent && dt == fw::DType::I32 && next && !p.eager_argmin && p.bs == fw::kTile;
+    // the direct-copy phase 3 (block 128, aligned rows): int32 with successors
+    // in packed keys, or 32-bit distances only
+    const bool direct = !persistent && p.bs == fw::kTile && p.vec && (packed || (!next && dt != fw::DType::F64));
+    if (direct) {
+        // operand panels (two parities, A' and B', 128 rows of 128 nt entries
+        // each), fix-up counters (one per phase-3 launch) and tile list
+        s = grow_ints(&p.work->panel, &p.work->panel_ints, 4 * (int64_t)fw::kTile * fw::kTile * p.nt,
+                      "operand panels");
+        if (s != FW_OK) return s;
+        s = grow_ints(&p.work->fix, &p.work->fix_ints, 2 * (int64_t)p.rounds + (int64_t)p.nt * p.nt, "fix-up list");
+        if (s != FW_OK) return s;
+    }
     hipError_t e = timed(tm, 0, p.stream, [&] { return fw::launch_init(p); });
     if (e == hipSuccess && direct) e = fw::launch_fix_reset(p);
     if (e != hipSuccess) return hip_fail(e, "init launch");

@@ -372,6 +372,12 @@ template <typename U, int ARGMIN> struct alignas(4 * sizeof(U)) MinplusSmem {
 constexpr uint32_t kPackLimit = 1u << 22;     // operand panels below this: packed keys
 constexpr uint32_t kPackSat = (1u << 23) - 1; // S: operands clamp here
 __device__ __forceinline__ uint32_t pack_a(uint32_t a) { return (a < kPackSat ? a : kPackSat) << 8; }
+// 32-bit entries as raw panel words and back (distances-only panels)
+__device__ __forceinline__ uint32_t to_bits(uint32_t v) { return v; }
+__device__ __forceinline__ uint32_t to_bits(float v) { return __float_as_uint(v); }
+template <typename U> __device__ __forceinline__ U from_bits(uint32_t w);
+template <> __device__ __forceinline__ uint32_t from_bits<uint32_t>(uint32_t w) { return w; }
+template <> __device__ __forceinline__ float from_bits<float>(uint32_t w) { return __uint_as_float(w); }
 __device__ __forceinline__ uint32_t pack_b(uint32_t b, int k) {
     return ((b < kPackSat ? b : kPackSat) << 8) | (uint32_t)(2 * k + 1);
 }
@@ -773,6 +779,29 @@ __device__ __forceinline__ void minplus_tile_impl(U *__restrict__ D, int32_t *__
             }
         }
     }
+    // ---- distances only (32-bit types): the band tiles write raw operand
+    // panels instead, same layout: B'[k][j] = D[b0 + k][j], A'[k][i] =
+    // D[i][b0 + k]
+    if constexpr (ARGMIN == 0 && sizeof(U) == 4) {
+        if (mode != 0 && panel) {
+            uint32_t *const pa = panel + (int64_t)(K & 1) * 2 * kTile * ppitch;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int li = G::row_off(tye, r);
+                if (li >= rows_valid) continue;
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    const int lj = G::col_off(txe, c);
+                    if (lj >= cols_valid) continue;
+                    const uint32_t v = to_bits(acc[r][c]);
+                    if (mode == 1)
+                        pa[(kTile + li) * ppitch + col0 + lj] = v;
+                    else
+                        pa[lj * ppitch + row0 + li] = v;
+                }
+            }
+        }
+    }
 
     // ---- store (rows / columns of the band itself are not part of phase 3)
 #pragma unroll
@@ -875,9 +904,10 @@ __device__ __forceinline__ int64_t phase3_tile(int part, int K, int nt) {
     return idx;
 }
 
-// panel (int32, deferred successors, block size 128; else null): the packed
-// operand panels, 2 x 2 x 128 rows of ppitch entries, written by the band
-// tiles (phase 2) for phase 3's direct-copy kernel.
+// panel (block size 128 and either int32 with deferred successors or 32-bit
+// distances only; else null): the operand panels, 2 x 2 x 128 rows of ppitch
+// entries, written by the band tiles (phase 2) for phase 3's direct-copy
+// kernel.
 template <typename U, int ARGMIN, int PHASE, bool VEC>
 __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves_standalone)) void minplus_kernel(
         U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int K, int BS, int nt,
@@ -901,27 +931,30 @@ __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves_s
 }
 
 // ------------------------------------------- phase 3: direct-copy kernel
-// The common case of phase 3 in the three-launch schedule -- int32 with
-// successors, block size = tile edge, packed keys, a full tile and band,
-// 16-byte aligned rows, row pitch <= 2^22 entries -- runs in a kernel of its
-// own, small enough (32 KB of LDS, <= 128 VGPRs) for four workgroups per CU:
-//   - operands: the band tiles also write the round's packed operand panels
-//     (A'[k][i] k-major and B'[k][j], round parity K & 1, rows of ppitch
-//     entries); each 16-k chunk of both is copied from memory straight into
-//     LDS with global_load_lds (gfx950's 16-byte direct-to-LDS load: no
-//     registers, no VALU work), double-buffered: chunk c + 1 is copied while
-//     chunk c is relaxed, one barrier per chunk;
+// The common case of phase 3 in the three-launch schedule -- block size = tile
+// edge, a full tile and band, 16-byte aligned rows, row pitch <= 2^22 entries,
+// and either int32 with successors in packed keys or 32-bit distances only --
+// runs in a kernel of its own, small enough (32 KB of LDS, <= 128 VGPRs) for
+// four workgroups per CU:
+//   - operands: the band tiles also write the round's operand panels (A'[k][i]
+//     k-major and B'[k][j], round parity K & 1, rows of ppitch entries; packed
+//     keys, or raw entries for distances only); each 16-k chunk of both is
+//     copied from memory straight into LDS with global_load_lds (gfx950's
+//     16-byte direct-to-LDS load: no registers, no VALU work),
+//     double-buffered: chunk c + 1 is copied while chunk c is relaxed, one
+//     barrier per chunk;
 //   - 256 threads with 8 x 8 entries each: eight 16-byte LDS reads feed 128
 //     relaxations per thread and pair of k's;
-//   - entry by entry, the two adds and the v_min3 that reads them are issued
+//   - entry by entry, the two adds and the min3 that reads them are issued
 //     together (empty asm statements pin the order; the compiler would
 //     otherwise issue all adds first): on gfx950 v_add issues at about twice
 //     the rate of v_min3, and this order lets the two overlap (measured);
 //   - every global address is a per-tile base in scalar registers plus a
-//     per-thread offset, there are no bounds or band tests, and a wave none
-//     of whose entries improved skips the successor gather and the stores.
-// Same arithmetic, k order and results as the general tile with packed keys.
-// A tile that does not qualify is appended to the launch's fix-up list, which
+//     per-thread offset, and there are no bounds or band tests; with
+//     successors, a wave none of whose entries improved skips the successor
+//     gather and the stores.
+// Same arithmetic, k order and results as the general tile.  A tile that does
+// not qualify is appended to the launch's fix-up list, which
 // minplus_fixup_kernel then runs with the general tile.
 constexpr int64_t kFullTileMaxLd = int64_t(1) << 22;
 constexpr int KCD = 16;                    // k's per chunk of the direct tile
@@ -930,33 +963,38 @@ struct alignas(16) DirectSmem {
     uint32_t Bs[2][KCD][kTile];            // Bs[buf][k][j] = B'[chunk k][j]
 };
 
-// One chunk of KCD k's into the keys, two k's per step.
-__device__ __forceinline__ void direct_chunk(const uint32_t (*__restrict__ As)[kTile],
-                                             const uint32_t (*__restrict__ Bs)[kTile], int tx, int ty,
-                                             uint32_t acc[8][8]) {
+// One chunk of KCD k's into the running minima, two k's per step.
+template <typename U>
+__device__ __forceinline__ void direct_chunk(const U (*__restrict__ As)[kTile], const U (*__restrict__ Bs)[kTile],
+                                             int tx, int ty, U acc[8][8]) {
 #pragma unroll 1
     for (int kk = 0; kk < KCD; kk += 2) {
-        uint32_t a[8], b[8], a2[8], b2[8];
-        lds_operands<uint32_t, 256, kTile>(As, Bs, kk, tx, ty, a, b);
-        lds_operands<uint32_t, 256, kTile>(As, Bs, kk + 1, tx, ty, a2, b2);
+        U a[8], b[8], a2[8], b2[8];
+        lds_operands<U, 256, kTile>(As, Bs, kk, tx, ty, a, b);
+        lds_operands<U, 256, kTile>(As, Bs, kk + 1, tx, ty, a2, b2);
 #pragma unroll
         for (int r = 0; r < 8; ++r)
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
-                uint32_t x = a[r] + b[c], y = a2[r] + b2[c];
+                U x = a[r] + b[c], y = a2[r] + b2[c];
                 asm volatile("" : "+v"(x), "+v"(y));
-                acc[r][c] = Arith<uint32_t>::mn(acc[r][c], Arith<uint32_t>::mn(x, y));
+                acc[r][c] = Arith<U>::mn(acc[r][c], Arith<U>::mn(x, y));
                 asm volatile("" : "+v"(acc[r][c]));
             }
     }
 }
 
-// fix_count / fix_list: this launch's fix-up counter (zeroed once per solve)
-// and the list of tiles the general kernel runs afterwards (nt^2 entries).
+// PACKED: int32 with successors, U = uint32_t holding keys; otherwise
+// distances only, U = uint32_t or float holding raw entries (NX and bmax are
+// not read).  fix_count / fix_list: this launch's fix-up counter (zeroed once
+// per solve) and the list of tiles the general kernel runs afterwards (nt^2
+// entries).
+template <typename U, bool PACKED>
 __global__ __launch_bounds__(256, 4) void minplus_direct_kernel(
-        uint32_t *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int K, int nt,
+        U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int K, int nt,
         const int *__restrict__ bmax, int part, const uint32_t *__restrict__ panel, int64_t ppitch,
         int *__restrict__ fix_count, int *__restrict__ fix_list) {
+    static_assert(sizeof(U) == 4 && (!PACKED || std::is_same<U, uint32_t>::value), "32-bit entries");
     __shared__ DirectSmem sm;
     using G = Geo<256>;
     const int64_t idx = phase3_tile(part, K, nt);
@@ -965,10 +1003,11 @@ __global__ __launch_bounds__(256, 4) void minplus_direct_kernel(
     const int64_t row0_ = (idx / nt) * kTile, col0_ = (idx % nt) * kTile;
     if (row0_ == b0 || col0_ == b0) return;                       // the band's own tiles
     {
-        const int *bm = bmax + (K & 1) * 2 * nt;
+        // with keys, both operand bands must stay below the packing limit
+        const int *bm = bmax + (PACKED ? (K & 1) * 2 * nt : 0);
         const bool direct = n - b0 >= kTile && row0_ + kTile <= n && col0_ + kTile <= n && ld <= kFullTileMaxLd &&
-                            (uint32_t)bm[nt + (int)(row0_ / kTile)] < kPackLimit &&
-                            (uint32_t)bm[(int)(col0_ / kTile)] < kPackLimit;
+                            (!PACKED || ((uint32_t)bm[nt + (int)(row0_ / kTile)] < kPackLimit &&
+                                         (uint32_t)bm[(int)(col0_ / kTile)] < kPackLimit));
         if (!direct) {
             if (threadIdx.x == 0) fix_list[atomicAdd(fix_count, 1)] = (int)idx;
             return;
@@ -1004,17 +1043,22 @@ __global__ __launch_bounds__(256, 4) void minplus_direct_kernel(
         }
     };
     copy_chunk(0, 0);
-    // C as keys (min(C, S) << 8)
+    // C: keys (min(C, S) << 8) with successors, raw entries without
     const char *const cbase = reinterpret_cast<const char *>(D) + row0 * pitch + col0 * 4;
-    uint32_t acc[8][8];
+    U acc[8][8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
         const int64_t ro = (int64_t)G::row_off(ty, r) * pitch;
 #pragma unroll
         for (int g = 0; g < 2; ++g) {
             const uint4 v = *reinterpret_cast<const uint4 *>(cbase + ro + (int64_t)G::col_off(tx, 4 * g) * 4);
-            acc[r][4 * g] = pack_a(v.x); acc[r][4 * g + 1] = pack_a(v.y);
-            acc[r][4 * g + 2] = pack_a(v.z); acc[r][4 * g + 3] = pack_a(v.w);
+            if constexpr (PACKED) {
+                acc[r][4 * g] = pack_a(v.x); acc[r][4 * g + 1] = pack_a(v.y);
+                acc[r][4 * g + 2] = pack_a(v.z); acc[r][4 * g + 3] = pack_a(v.w);
+            } else {
+                acc[r][4 * g] = from_bits<U>(v.x); acc[r][4 * g + 1] = from_bits<U>(v.y);
+                acc[r][4 * g + 2] = from_bits<U>(v.z); acc[r][4 * g + 3] = from_bits<U>(v.w);
+            }
         }
     }
 #pragma unroll
@@ -1022,45 +1066,62 @@ __global__ __launch_bounds__(256, 4) void minplus_direct_kernel(
         wait_vmem();                               // this wave's copies of chunk c (and C)
         __syncthreads();                           // everyone's; and chunk c - 1 is consumed
         if (c + 1 < kTile / KCD) copy_chunk((c + 1) * KCD, (c + 1) & 1);
-        direct_chunk(sm.As[c & 1], sm.Bs[c & 1], tx, ty, acc);
+        direct_chunk<U>(reinterpret_cast<const U (*)[kTile]>(sm.As[c & 1]),
+                        reinterpret_cast<const U (*)[kTile]>(sm.Bs[c & 1]), tx, ty, acc);
     }
-    // Keys -> results, row by row: bit 0 = improved, bits 1..7 = k, bits 8.. =
-    // value.  The successor of an improved entry is A's, NX[i][b0 + k] (the
-    // column band is not written during phase 3); only improved entries are
-    // stored, four at once only when all four improved (an unimproved key
-    // holds min(C, S), not C).
-    uint32_t any = 0;
+    if constexpr (!PACKED) {
+        // distances only: the tile's new values, four at a time
+        char *const Db = reinterpret_cast<char *>(D);
 #pragma unroll
-    for (int r = 0; r < 8; ++r)
+        for (int r = 0; r < 8; ++r) {
+            const int64_t ro = (row0 + G::row_off(ty, r)) * pitch;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) any |= acc[r][c];
-    if (!__builtin_amdgcn_ballot_w64((any & 1u) != 0)) return;
-    char *const Db = reinterpret_cast<char *>(D);
-    char *const Nb = reinterpret_cast<char *>(NX);
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int64_t ro = (row0 + G::row_off(ty, r)) * pitch;
-        const char *const na = Nb + ro + b0 * 4;
-        int32_t nxv[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            nxv[c] = -1;
-            if (acc[r][c] & 1u) nxv[c] = *reinterpret_cast<const int32_t *>(na + ((acc[r][c] >> 1) & 127u) * 4u);
+            for (int g = 0; g < 2; ++g) {
+                const U *e = &acc[r][4 * g];
+                *reinterpret_cast<uint4 *>(Db + ro + (col0 + G::col_off(tx, 4 * g)) * 4) =
+                        make_uint4(to_bits(e[0]), to_bits(e[1]), to_bits(e[2]), to_bits(e[3]));
+            }
         }
+    } else {
+        // Keys -> results, row by row: bit 0 = improved, bits 1..7 = k, bits
+        // 8.. = value.  The successor of an improved entry is A's,
+        // NX[i][b0 + k] (the column band is not written during phase 3); only
+        // improved entries are stored, four at once only when all four
+        // improved (an unimproved key holds min(C, S), not C).
+        uint32_t any = 0;
 #pragma unroll
-        for (int g = 0; g < 2; ++g) {
-            const int64_t co = (col0 + G::col_off(tx, 4 * g)) * 4;
-            uint32_t *dp = reinterpret_cast<uint32_t *>(Db + ro + co);
-            int32_t *np = reinterpret_cast<int32_t *>(Nb + ro + co);
-            const uint32_t *e = &acc[r][4 * g];
-            const bool all = (e[0] & e[1] & e[2] & e[3] & 1u) != 0;
-            if (all) {
-                *reinterpret_cast<uint4 *>(dp) = make_uint4(e[0] >> 8, e[1] >> 8, e[2] >> 8, e[3] >> 8);
-                *reinterpret_cast<int4 *>(np) = make_int4(nxv[4 * g], nxv[4 * g + 1], nxv[4 * g + 2], nxv[4 * g + 3]);
-            } else {
+        for (int r = 0; r < 8; ++r)
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (e[q] & 1u) { dp[q] = e[q] >> 8; np[q] = nxv[4 * g + q]; }
+            for (int c = 0; c < 8; ++c) any |= acc[r][c];
+        if (!__builtin_amdgcn_ballot_w64((any & 1u) != 0)) return;
+        char *const Db = reinterpret_cast<char *>(D);
+        char *const Nb = reinterpret_cast<char *>(NX);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int64_t ro = (row0 + G::row_off(ty, r)) * pitch;
+            const char *const na = Nb + ro + b0 * 4;
+            int32_t nxv[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                nxv[c] = -1;
+                if (acc[r][c] & 1u) nxv[c] = *reinterpret_cast<const int32_t *>(na + ((acc[r][c] >> 1) & 127u) * 4u);
+            }
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                const int64_t co = (col0 + G::col_off(tx, 4 * g)) * 4;
+                uint32_t *dp = reinterpret_cast<uint32_t *>(Db + ro + co);
+                int32_t *np = reinterpret_cast<int32_t *>(Nb + ro + co);
+                const uint32_t *e = &acc[r][4 * g];
+                const bool all = (e[0] & e[1] & e[2] & e[3] & 1u) != 0;
+                if (all) {
+                    *reinterpret_cast<uint4 *>(dp) = make_uint4(e[0] >> 8, e[1] >> 8, e[2] >> 8, e[3] >> 8);
+                    *reinterpret_cast<int4 *>(np) =
+                            make_int4(nxv[4 * g], nxv[4 * g + 1], nxv[4 * g + 2], nxv[4 * g + 3]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (e[q] & 1u) { dp[q] = e[q] >> 8; np[q] = nxv[4 * g + q]; }
+                }
             }
         }
     }
@@ -1068,18 +1129,18 @@ __global__ __launch_bounds__(256, 4) void minplus_direct_kernel(
 
 // The fix-up tiles of a direct-copy launch, with the general tile (packed
 // keys or not, ragged or not); a resident-size grid walks the list.
-template <bool VEC>
-__global__ __launch_bounds__((Occ<uint32_t, 2>::threads), (Occ<uint32_t, 2>::waves_standalone)) void
-minplus_fixup_kernel(uint32_t *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int K, int nt,
+template <typename U, int ARGMIN, bool VEC>
+__global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves_standalone)) void
+minplus_fixup_kernel(U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int K, int nt,
                      int *__restrict__ bmax, const int *__restrict__ fix_count, const int *__restrict__ fix_list) {
-    __shared__ MinplusSmem<uint32_t, 2> sm;
+    __shared__ MinplusSmem<U, ARGMIN> sm;
     const int count = __hip_atomic_load(fix_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int64_t b0 = (int64_t)K * kTile;
     const int64_t b1 = b0 + imin64((int64_t)kTile, n - b0);
     for (int q = blockIdx.x; q < count; q += gridDim.x) {
         int64_t row0, col0;
         if (band_tile(0, fix_list[q], n, b0, b1, nt, row0, col0))
-            minplus_tile<uint32_t, 2, VEC>(D, NX, n, ld, K, kTile, 0, row0, col0, sm, bmax, nt);
+            minplus_tile<U, ARGMIN, VEC>(D, NX, n, ld, K, kTile, 0, row0, col0, sm, bmax, nt);
         __syncthreads();                           // LDS is reused by the next tile
     }
 }
@@ -1619,22 +1680,26 @@ hipError_t phase1_t(const Plan &p, int K) {
 template <typename U, int ARGMIN, bool VEC>
 hipError_t minplus_t(const Plan &p, int K, int phase, int part) {
     constexpr int NT = Occ<U, ARGMIN>::threads;
-    int *bmax = (ARGMIN == 2 && std::is_same<U, uint32_t>::value) ? p.work->bmax : nullptr;
-    uint32_t *panel = (bmax && p.bs == kTile) ? reinterpret_cast<uint32_t *>(p.work->panel) : nullptr;
+    // the direct-copy phase 3 (block 128, aligned rows): int32 with
+    // successors in packed keys, or 32-bit distances only
+    constexpr bool PACKED = ARGMIN == 2 && std::is_same<U, uint32_t>::value;
+    constexpr bool DIRECT = VEC && (PACKED || (ARGMIN == 0 && sizeof(U) == 4));
+    int *bmax = PACKED ? p.work->bmax : nullptr;
+    uint32_t *panel = (DIRECT && p.bs == kTile) ? reinterpret_cast<uint32_t *>(p.work->panel) : nullptr;
     const int64_t ppitch = (int64_t)p.nt * kTile;
-    if constexpr (ARGMIN == 2 && VEC && std::is_same<U, uint32_t>::value) {
+    if constexpr (DIRECT) {
         if (phase == 3 && panel) {
             // direct-copy tiles, then the general tile on the ones that did not qualify
             const int64_t tiles = (int64_t)p.nt * p.nt;
             const unsigned grid = part == 1 ? (unsigned)(2 * p.nt) : (unsigned)(8 * ((tiles + 7) / 8));
             int *cnt = p.work->fix + 2 * K + (part == 2 ? 1 : 0);
             int *list = p.work->fix + 2 * (int64_t)p.rounds;
-            hipLaunchKernelGGL(minplus_direct_kernel, dim3(grid), dim3(256), 0, p.stream, (uint32_t *)p.dist, p.next,
-                               p.n, p.ld, K, p.nt, bmax, part, panel, ppitch, cnt, list);
+            hipLaunchKernelGGL((minplus_direct_kernel<U, PACKED>), dim3(grid), dim3(256), 0, p.stream, (U *)p.dist,
+                               p.next, p.n, p.ld, K, p.nt, bmax, part, panel, ppitch, cnt, list);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
             const unsigned fgrid = (unsigned)imin64(part == 1 ? 2 * (int64_t)p.nt : tiles, 512);
-            hipLaunchKernelGGL((minplus_fixup_kernel<VEC>), dim3(fgrid), dim3(NT), 0, p.stream, (uint32_t *)p.dist,
+            hipLaunchKernelGGL((minplus_fixup_kernel<U, ARGMIN, VEC>), dim3(fgrid), dim3(NT), 0, p.stream, (U *)p.dist,
                                p.next, p.n, p.ld, K, p.nt, bmax, cnt, list);
             return hipGetLastError();
         }
