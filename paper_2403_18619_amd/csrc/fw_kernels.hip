@@ -951,7 +951,7 @@ __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves_s
 //     the rate of v_min3, and this order lets the two overlap (measured);
 //   - every global address is a per-tile base in scalar registers plus a
 //     per-thread offset, and there are no bounds or band tests; with
-//     successors, a wave none of whose entries improved skips the successor
+//     successors, a tile none of whose entries improved skips the successor
 //     gather and the stores.
 // Same arithmetic, k order and results as the general tile.  A tile that does
 // not qualify is appended to the launch's fix-up list, which
@@ -1083,44 +1083,63 @@ __global__ __launch_bounds__(256, 4) void minplus_direct_kernel(
             }
         }
     } else {
-        // Keys -> results, row by row: bit 0 = improved, bits 1..7 = k, bits
-        // 8.. = value.  The successor of an improved entry is A's,
-        // NX[i][b0 + k] (the column band is not written during phase 3); only
+        // Keys -> results: bit 0 = improved, bits 1..7 = k, bits 8.. = value.
+        // The successor of an improved entry is A's, NX[i][b0 + k] (the
+        // column band is not written during phase 3).  That 128 x 128 block
+        // of NX is copied into the LDS the operands no longer need, 64 rows at
+        // a time (the same direct-to-LDS copy), and gathered from there.  Only
         // improved entries are stored, four at once only when all four
-        // improved (an unimproved key holds min(C, S), not C).
+        // improved (an unimproved key holds min(C, S), not C).  The barrier
+        // that ends the operand reads also tells whether any entry of the
+        // tile improved; if none did, the workgroup is done.
         uint32_t any = 0;
 #pragma unroll
         for (int r = 0; r < 8; ++r)
 #pragma unroll
             for (int c = 0; c < 8; ++c) any |= acc[r][c];
-        if (!__builtin_amdgcn_ballot_w64((any & 1u) != 0)) return;
+        if (!__syncthreads_or((int)(any & 1u))) return;
         char *const Db = reinterpret_cast<char *>(D);
         char *const Nb = reinterpret_cast<char *>(NX);
+        int32_t (*const NXs)[kTile] = reinterpret_cast<int32_t (*)[kTile]>(&sm);   // 64 rows, 32 KB
+        static_assert(sizeof(DirectSmem) == 64 * kTile * sizeof(int32_t), "LDS for half the successor block");
+        const char *const nband = Nb + row0 * pitch + b0 * 4;
+        const uint32_t noff = (uint32_t)(lane >> 5) * (uint32_t)pitch + (uint32_t)(lane & 31) * 16u;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int64_t ro = (row0 + G::row_off(ty, r)) * pitch;
-            const char *const na = Nb + ro + b0 * 4;
-            int32_t nxv[8];
+        for (int h = 0; h < 2; ++h) {
+            if (h) __syncthreads();                // the first half is consumed
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                nxv[c] = -1;
-                if (acc[r][c] & 1u) nxv[c] = *reinterpret_cast<const int32_t *>(na + ((acc[r][c] >> 1) & 127u) * 4u);
+            for (int q = 0; q < 8; ++q) {
+                const int x = 8 * q + 2 * wv;      // rows x, x + 1 of this half
+                __builtin_amdgcn_global_load_lds(
+                        (const __attribute__((address_space(1))) void *)(nband + (int64_t)(64 * h + x) * pitch + noff),
+                        (__attribute__((address_space(3))) void *)&NXs[x][0], 16, 0, 0);
             }
+            wait_vmem();
+            __syncthreads();
 #pragma unroll
-            for (int g = 0; g < 2; ++g) {
-                const int64_t co = (col0 + G::col_off(tx, 4 * g)) * 4;
-                uint32_t *dp = reinterpret_cast<uint32_t *>(Db + ro + co);
-                int32_t *np = reinterpret_cast<int32_t *>(Nb + ro + co);
-                const uint32_t *e = &acc[r][4 * g];
-                const bool all = (e[0] & e[1] & e[2] & e[3] & 1u) != 0;
-                if (all) {
-                    *reinterpret_cast<uint4 *>(dp) = make_uint4(e[0] >> 8, e[1] >> 8, e[2] >> 8, e[3] >> 8);
-                    *reinterpret_cast<int4 *>(np) =
-                            make_int4(nxv[4 * g], nxv[4 * g + 1], nxv[4 * g + 2], nxv[4 * g + 3]);
-                } else {
+            for (int rr = 0; rr < 4; ++rr) {
+                const int r = 4 * h + rr;
+                const int li = G::row_off(ty, r);  // 64 h + local row
+                const int32_t *const nrow = NXs[li - 64 * h];
+                const int64_t ro = (row0 + li) * pitch;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (e[q] & 1u) { dp[q] = e[q] >> 8; np[q] = nxv[4 * g + q]; }
+                for (int g = 0; g < 2; ++g) {
+                    const int64_t co = (col0 + G::col_off(tx, 4 * g)) * 4;
+                    uint32_t *dp = reinterpret_cast<uint32_t *>(Db + ro + co);
+                    int32_t *np = reinterpret_cast<int32_t *>(Nb + ro + co);
+                    const uint32_t *e = &acc[r][4 * g];
+                    int32_t nxv[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) nxv[q] = nrow[(e[q] >> 1) & 127u];   // k = 0 when unimproved
+                    const bool all = (e[0] & e[1] & e[2] & e[3] & 1u) != 0;
+                    if (all) {
+                        *reinterpret_cast<uint4 *>(dp) = make_uint4(e[0] >> 8, e[1] >> 8, e[2] >> 8, e[3] >> 8);
+                        *reinterpret_cast<int4 *>(np) = make_int4(nxv[0], nxv[1], nxv[2], nxv[3]);
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (e[q] & 1u) { dp[q] = e[q] >> 8; np[q] = nxv[q]; }
+                    }
                 }
             }
         }
