@@ -107,11 +107,13 @@ typedef struct fw_options {
  * The _ex forms take options (NULL = defaults).  Library-owned device memory
  * (per device, allocated on first use, grown on demand, kept until exit):
  * besides the small workspace, an int32 solve with successors in the
- * three-launch schedule keeps 2 x ceil(n/128) band maxima and, at block size
- * 128, the rounds' packed operand panels, 4 x 128 x 128 ceil(n/128) int32
- * (64 MiB at n = 32768), and a phase-3 fix-up list of 2 R + ceil(n/128)^2
- * int32 (R rounds); a call that has to grow them allocates, so capture a
- * solve in a hipGraph after one uncaptured call of the same or larger n. */
+ * three-launch schedule keeps 2 x ceil(n/128) band maxima; at block size 128
+ * with 16-byte aligned rows, that solve and a 32-bit solve without
+ * successors keep the rounds' operand panels, 4 x 128 x 128 ceil(n/128)
+ * int32 (64 MiB at n = 32768), and a phase-3 fix-up list of
+ * 2 R + ceil(n/128)^2 int32 (R rounds); a call that has to grow them
+ * allocates, so capture a solve in a hipGraph after one uncaptured call of the
+ * same or larger n. */
 fw_status fw_solve_i32(int32_t *dist, int32_t *next, int64_t n, int64_t ld, void *stream);
 fw_status fw_solve_f32(float *dist, int32_t *next, int64_t n, int64_t ld, void *stream);
 fw_status fw_solve_ex_i32(int32_t *dist, int32_t *next, int64_t n, int64_t ld,
