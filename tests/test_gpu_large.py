@@ -7,6 +7,8 @@ times (default block size and schedule).
     relative 1e-5, successor walks on sampled rows;
   - n = 32768 headline graph: Dijkstra from sampled sources (rows 0, n-1 and
     seeded random rows), bit-exact, walks and triangle inequality on them.
+The two larger cases also solve for distances only (a phase 3 of its own)
+and require the same bits as the solve with successors.
 """
 import numpy as np
 import pytest
@@ -18,11 +20,11 @@ from tests.gpu_helpers import INF, assert_close_f32, assert_walks, log
 pytestmark = pytest.mark.gpu
 
 
-def _solve_device(W, flags=0):
+def _solve_device(W, flags=0, next_hop=True):
     import torch
     import paper_2403_18619_amd as fw
     Wd = torch.from_numpy(W).cuda()
-    D, NX = fw.solve(Wd, flags=flags)
+    D, NX = fw.solve(Wd, next_hop=next_hop, flags=flags)
     fw.check()
     del Wd
     return D, NX
@@ -47,6 +49,9 @@ def test_dense_f32_n8192_full():
     D2, N2 = _solve_device(W, flags=fw.FLAG_EAGER_ARGMIN)
     assert torch.equal(Dg.view(torch.int32), D2.view(torch.int32)) and torch.equal(NXg, N2)
     del D2, N2
+    D3, _ = _solve_device(W, next_hop=False)
+    assert torch.equal(Dg.view(torch.int32), D3.view(torch.int32))
+    del D3
     Dg, NXg = Dg.cpu().numpy(), NXg.cpu().numpy()
     D64, _ = oracle.fw_f64(W, next_hop=False)
     assert_close_f32(Dg, D64)
@@ -63,6 +68,9 @@ def test_headline_n32768_sampled_rows():
     Dr = D[torch_index(rows)].cpu().numpy()
     ref = oracle.sssp_i32(W, rows)
     np.testing.assert_array_equal(Dr, ref)
+    Dd, _ = _solve_device(W, next_hop=False)
+    assert torch_equal(D, Dd)
+    del Dd
     # walks on the sampled rows need the full successor matrix on the host
     Dh, NXh = D.cpu().numpy(), NX.cpu().numpy()
     del D, NX
@@ -73,6 +81,11 @@ def test_headline_n32768_sampled_rows():
     for k in ks:
         assert (Di <= Di[:, k:k + 1] + Dh[k].astype(np.int64)[None, :]).all()
     assert (Dh[rows] <= np.where(W[rows] >= INF, INF, W[rows])).all()        # D <= W
+
+
+def torch_equal(a, b):
+    import torch
+    return torch.equal(a, b)
 
 
 def torch_index(rows):
