@@ -272,45 +272,59 @@ def main():
     stream = torch.cuda.current_stream()
     bs = args.block or 128
 
-    def step(flags):
-        D.copy_(Wd)
-        fw.solve_(D, NX, block=args.block, schedule=args.schedule, flags=flags, stream=stream)
+    def measure(nx, steps, warmup):
+        """Warm up, then time `steps` solves (distances, and successors when
+        nx is given): ms per step and the roofline of the dominant kernel."""
+        def step(flags):
+            D.copy_(Wd)
+            fw.solve_(D, nx, block=args.block, schedule=args.schedule, flags=flags, stream=stream)
 
-    log(f"warmup x{args.warmup}")
-    for _ in range(args.warmup):
-        step(0)
-    torch.cuda.synchronize()
-    fw.check()
-    fw.phase_times()
+        log(f"warmup x{warmup} ({'dist + next' if nx is not None else 'dist only'})")
+        for _ in range(warmup):
+            step(0)
+        torch.cuda.synchronize()
+        fw.check()
+        fw.phase_times()
 
-    log(f"timing x{args.steps}")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        step(fw.FLAG_TIME_PHASES)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    fw.check()
-    ph = fw.phase_times()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+        log(f"timing x{steps}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(fw.FLAG_TIME_PHASES)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        fw.check()
+        ph = fw.phase_times()
+        ms = (t1 - t0) * 1e3 / steps
+        log(f"{ms:.1f} ms/step, {n ** 3 / (ms / 1e3):.4g} relaxations/s")
+
+        # dominant kernel: phase 3 (or the persistent kernel)
+        kind = "persistent" if ph["persistent"][1] else "phase3"
+        k_ms, k_launches = ph[kind]
+        relax_per_solve = phase3_relaxations(n, bs) if kind == "phase3" else n ** 3
+        relax_per_launch = relax_per_solve / (k_launches / steps)
+        avg_s = k_ms / k_launches / 1e3
+        ops = OPS_PER_RELAX[args.dtype]
+        achieved = ops * relax_per_launch / avg_s
+        traffic = load_traffic(f"{args.dtype}_n{n}_bs{bs}_{'next' if nx is not None else 'dist'}")
+        peak = VALU_PEAK_LANE_OPS[args.dtype]
+        roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                    "unit": "Top/s", "frac": achieved / peak, "traffic": traffic,
+                    "kernel": kind, "avg_launch_ms": avg_s * 1e3, "launches_per_step": k_launches / steps,
+                    "ops_per_relaxation": ops}
+        phase_ms = {k: (v[0] / steps) for k, v in ph.items() if v[1]}
+        return ms, roofline, phase_ms
+
+    ms_per_step, roofline, phase_ms = measure(NX, args.steps, args.warmup)
     value = n ** 3 / (ms_per_step / 1e3)
-    log(f"{ms_per_step:.1f} ms/step, {value:.4g} relaxations/s")
 
-    # dominant kernel: phase 3 (or the persistent kernel)
-    kind = "persistent" if ph["persistent"][1] else "phase3"
-    k_ms, k_launches = ph[kind]
-    relax_per_solve = phase3_relaxations(n, bs) if kind == "phase3" else n ** 3
-    relax_per_launch = relax_per_solve / (k_launches / args.steps)
-    avg_s = k_ms / k_launches / 1e3
-    ops = OPS_PER_RELAX[args.dtype]
-    achieved = ops * relax_per_launch / avg_s
-    traffic = load_traffic(f"{args.dtype}_n{n}_bs{bs}_{'next' if NX is not None else 'dist'}")
-    peak = VALU_PEAK_LANE_OPS[args.dtype]
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                "unit": "Top/s", "frac": achieved / peak, "traffic": traffic,
-                "kernel": kind, "avg_launch_ms": avg_s * 1e3, "launches_per_step": k_launches / args.steps,
-                "ops_per_relaxation": ops}
-    phase_ms = {k: (v[0] / args.steps) for k, v in ph.items() if v[1]}
+    # the same graph for distances only, reported beside the primary result
+    dist_only = None
+    if NX is not None and not args.no_extras:
+        d_ms, d_roof, d_phase = measure(None, args.steps, 1)
+        dist_only = {"workload": "the same graph, distances only (next = NULL)", "steps": args.steps,
+                     "ms_per_step": d_ms, "value": n ** 3 / (d_ms / 1e3), "unit": "relaxations/s",
+                     "roofline": d_roof, "phase_ms_per_step": d_phase}
 
     has_next = NX is not None
     del D, NX, Wd
@@ -341,6 +355,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phase_ms_per_step": phase_ms,
+        "dist_only": dist_only,
         "batched": batched,
         "fwdbwd": fwdbwd,
     }
