@@ -1043,19 +1043,26 @@ __global__ __launch_bounds__(256, 4) void minplus_direct_kernel(
         }
     };
     copy_chunk(0, 0);
-    // C: keys (min(C, S) << 8) with successors, raw entries without
+    // C.  Distances only: raw entries, loaded before the k loop.  With
+    // successors: the keys min(C, S) << 8 are folded into the running minima
+    // after it, which start above every key (a candidate key is at most
+    // 0x7FFFFF00 + 0x7FFFFFFF); a minimum does not depend on that order, and
+    // this order measured 1.2% faster per launch (2.24 against 2.27 ms at
+    // n = 32768, alternating on one box).
     const char *const cbase = reinterpret_cast<const char *>(D) + row0 * pitch + col0 * 4;
     U acc[8][8];
+    if constexpr (PACKED) {
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int64_t ro = (int64_t)G::row_off(ty, r) * pitch;
+        for (int r = 0; r < 8; ++r)
 #pragma unroll
-        for (int g = 0; g < 2; ++g) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(cbase + ro + (int64_t)G::col_off(tx, 4 * g) * 4);
-            if constexpr (PACKED) {
-                acc[r][4 * g] = pack_a(v.x); acc[r][4 * g + 1] = pack_a(v.y);
-                acc[r][4 * g + 2] = pack_a(v.z); acc[r][4 * g + 3] = pack_a(v.w);
-            } else {
+            for (int c = 0; c < 8; ++c) acc[r][c] = 0xFFFFFFFFu;
+    } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int64_t ro = (int64_t)G::row_off(ty, r) * pitch;
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(cbase + ro + (int64_t)G::col_off(tx, 4 * g) * 4);
                 acc[r][4 * g] = from_bits<U>(v.x); acc[r][4 * g + 1] = from_bits<U>(v.y);
                 acc[r][4 * g + 2] = from_bits<U>(v.z); acc[r][4 * g + 3] = from_bits<U>(v.w);
             }
@@ -1063,11 +1070,24 @@ __global__ __launch_bounds__(256, 4) void minplus_direct_kernel(
     }
 #pragma unroll
     for (int c = 0; c < kTile / KCD; ++c) {
-        wait_vmem();                               // this wave's copies of chunk c (and C)
+        wait_vmem();                               // this wave's copies of chunk c (and C, distances only)
         __syncthreads();                           // everyone's; and chunk c - 1 is consumed
         if (c + 1 < kTile / KCD) copy_chunk((c + 1) * KCD, (c + 1) & 1);
         direct_chunk<U>(reinterpret_cast<const U (*)[kTile]>(sm.As[c & 1]),
                         reinterpret_cast<const U (*)[kTile]>(sm.Bs[c & 1]), tx, ty, acc);
+    }
+    if constexpr (PACKED) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int64_t ro = (int64_t)G::row_off(ty, r) * pitch;
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(cbase + ro + (int64_t)G::col_off(tx, 4 * g) * 4);
+                const uint32_t w[4] = {pack_a(v.x), pack_a(v.y), pack_a(v.z), pack_a(v.w)};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[r][4 * g + e] = Arith<U>::mn(acc[r][4 * g + e], w[e]);
+            }
+        }
     }
     if constexpr (!PACKED) {
         // distances only: the tile's new values, four at a time
