@@ -139,8 +139,9 @@ def sssp_f64(W, sources, nthreads: int = 0):
     return out
 
 
-def validate_walk(W, D, NX, rows=None, rtol: float = 1e-5):
+def validate_walk(W, D, NX, rows=None, rtol: float = 1e-5, lib=None):
     """Walk-check rows of (D, NX) against W.  Returns (n_bad, (i, j, reason))."""
+    lib = lib or _L()
     n = D.shape[0]
     rows = np.arange(n, dtype=np.int64) if rows is None else np.ascontiguousarray(rows, np.int64)
     first = np.zeros(3, np.int64)
@@ -148,18 +149,18 @@ def validate_walk(W, D, NX, rows=None, rtol: float = 1e-5):
     if np.issubdtype(D.dtype, np.integer):
         W = np.ascontiguousarray(W, np.int32)
         D = np.ascontiguousarray(D, np.int32)
-        bad = _L().validate_walk_i32(W.ctypes.data, W.shape[1], D.ctypes.data, NX.ctypes.data,
+        bad = lib.validate_walk_i32(W.ctypes.data, W.shape[1], D.ctypes.data, NX.ctypes.data,
                                      D.shape[1], n, rows.ctypes.data, len(rows), first.ctypes.data)
     elif D.dtype == np.float64:
         W = np.ascontiguousarray(W, np.float64)
         D = np.ascontiguousarray(D, np.float64)
-        bad = _L().validate_walk_f64(W.ctypes.data, W.shape[1], D.ctypes.data, NX.ctypes.data,
+        bad = lib.validate_walk_f64(W.ctypes.data, W.shape[1], D.ctypes.data, NX.ctypes.data,
                                      D.shape[1], n, rows.ctypes.data, len(rows), rtol,
                                      first.ctypes.data)
     else:
         W = np.ascontiguousarray(W, np.float32)
         D = np.ascontiguousarray(D, np.float32)
-        bad = _L().validate_walk_f32(W.ctypes.data, W.shape[1], D.ctypes.data, NX.ctypes.data,
+        bad = lib.validate_walk_f32(W.ctypes.data, W.shape[1], D.ctypes.data, NX.ctypes.data,
                                      D.shape[1], n, rows.ctypes.data, len(rows), rtol,
                                      first.ctypes.data)
     return int(bad), tuple(int(x) for x in first)

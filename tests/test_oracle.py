@@ -50,6 +50,139 @@ def check_all_pins_i32(W, lib=None, unique_check=False):
     return fails, D, NX
 
 
+def _broken_cases(W, D, NX, inf):
+    """Plausible wrong (D, NX) pairs derived from a correct one, each with the
+    validator's reason code and the pair it must name first."""
+    n = D.shape[0]
+    fin = np.isfinite(D) if D.dtype.kind == "f" else (D < inf)
+    cases = []
+    D1 = D.copy(); D1[0, 0] = 1
+    cases.append(("nonzero diagonal", D1, NX, (0, 0, 1)))
+    N1 = NX.copy(); N1[1, 1] = 0
+    cases.append(("diagonal successor", D, N1, (1, 1, 1)))
+    i, j = [int(x) for x in np.argwhere(fin & ~np.eye(n, dtype=bool))[0]]
+    N2 = NX.copy(); N2[i, j] = -1
+    cases.append(("finite distance without successor", D, N2, (i, j, 2)))
+    D2 = D.copy(); D2[i, j] = inf
+    cases.append(("infinite distance with a successor", D2, NX, (i, j, 2)))
+    if D.dtype.kind == "f":
+        D3 = D.copy(); D3[i, j] = -np.inf
+        cases.append(("negative infinite distance", D3, NX, (i, j, 2)))
+        N3b = NX.copy(); N3b[i, j] = -1
+        cases.append(("negative infinite distance without successor", D3, N3b, (i, j, 2)))
+    N3 = NX.copy(); N3[i, j] = i
+    cases.append(("walk that stays put", D, N3, (i, j, 3)))
+    N4 = NX.copy(); N4[i, j] = n
+    cases.append(("successor out of range", D, N4, (i, j, 3)))
+    # a walk that loops: i -> h -> i -> ... toward j (both hops are edges)
+    h = next(v for v in range(n) if v not in (i, j))
+    N5 = NX.copy(); N5[i, j] = h; N5[h, j] = i
+    cases.append(("walk that loops", D, N5, (min(i, h), j, 3)))
+    D6 = D.copy()
+    D6[i, j] = D6[i, j] * 1.001 + (1 if D.dtype.kind != "f" else 0)
+    cases.append(("sum differs", D6, NX, (i, j, 4)))
+    return cases
+
+
+def check_validator_pins(kind, lib=None):
+    """The walk validator must accept correct outputs (closed forms and the
+    pinned oracle's) and reject each broken variant with its reason code.
+    Returns a list of failures (empty when every pin holds)."""
+    fails = []
+    n = 12
+    rtol = 1e-5
+    if kind == "i32":
+        W = synth.graph_i32(n, 61, 1.0, 1, 100)
+        D, NX = oracle.fw_i32(W)
+        inf = INF
+        Wc, Dc, NXc = P.chain(n, np.arange(1, n))
+        Wc, Dc, NXc = Wc.astype(np.int32), Dc.astype(np.int32), NXc.astype(np.int32)
+    else:
+        W = synth.graph_f32(n, 61, 1.0, 0.5, 1.5)
+        D, NX = oracle.fw_f64(W)
+        inf = np.inf
+        Wc, Dc, NXc = P.chain(n, np.arange(1, n))
+        Wc = np.where(Wc >= INF, np.inf, Wc)
+        Dc = np.where(Dc >= INF, np.inf, Dc)
+        NXc = NXc.astype(np.int32)
+        if kind == "f32":
+            W, D, Wc, Dc = W.astype(np.float32), D.astype(np.float32), Wc.astype(np.float32), Dc.astype(np.float32)
+        else:
+            W, Wc = W.astype(np.float64), Wc.astype(np.float64)
+    # acceptance: the oracle's answer, the closed-form chain, and a sum off by
+    # less than the tolerance
+    if oracle.validate_walk(W, D, NX, rtol=rtol, lib=lib)[0] != 0:
+        fails.append("rejects a correct answer")
+    if oracle.validate_walk(Wc, Dc, NXc, rtol=rtol, lib=lib)[0] != 0:
+        fails.append("rejects the closed-form chain")
+    if kind != "i32":
+        Dn = D.copy()
+        Dn[0, 5] = Dn[0, 5] * (1 + rtol / 4)
+        if oracle.validate_walk(W, Dn, NX, rtol=rtol, lib=lib)[0] != 0:
+            fails.append("rejects a sum within the tolerance")
+    for name, Db, Nb, exp in _broken_cases(W, D, NX, inf):
+        bad, first = oracle.validate_walk(W, Db, Nb, rtol=rtol, lib=lib)
+        if bad < 1 or first != exp:
+            fails.append(f"{name}: got {bad} bad, first {first}, expected {exp}")
+    # a hop over an absent edge: on the chain 0 -> 1 -> 2, claim 0 -> 2 directly
+    Nb = NXc.copy(); Nb[0, 2] = 2
+    bad, first = oracle.validate_walk(Wc, Dc, Nb, rtol=rtol, lib=lib)
+    if bad < 1 or first != (0, 2, 3):
+        fails.append(f"walk over an absent edge: got {bad}, {first}")
+    return fails
+
+
+@pytest.mark.parametrize("kind", ["i32", "f32", "f64"])
+def test_validator_pins(kind):
+    """Every reason code of the walk validator, for each element type."""
+    fails = check_validator_pins(kind)
+    assert not fails, fails
+
+
+def test_f32_oracle_successor_unique_paths():
+    """Float32 oracle on continuous weights (complete graph, U[0.5, 1.5):
+    unique shortest paths almost surely).  Distances against float64
+    Dijkstra within float32 rounding of a few hops; successors equal the
+    Bellman first hop except where the oracle's choice is itself shortest
+    within that rounding (a float32 near-tie)."""
+    fails = check_f32_oracle_pins()
+    assert not fails, fails
+
+
+def check_f32_oracle_pins(lib=None):
+    fails = []
+    # integer-valued float weights: every sum is exact
+    Wi = synth.graph_i32(90, 62, 0.3, 1, 50)
+    Wf = np.where(Wi >= INF, np.inf, Wi).astype(np.float32)
+    D32, N32 = oracle.fw_f32(Wf, lib=lib)
+    R = oracle.sssp_i32(Wi, np.arange(90))
+    if not (D32 == np.where(R >= INF, np.inf, R).astype(np.float32)).all():
+        fails.append("integer-valued distances differ from Dijkstra")
+    if oracle.validate_walk(Wf, D32, N32, rtol=0.0)[0] != 0:
+        fails.append("integer-valued walks")
+    # continuous weights
+    n = 120
+    W = synth.graph_f32(n, 63, 1.0, 0.5, 1.5)
+    D32, N32 = oracle.fw_f32(W, lib=lib)
+    Dd = oracle.sssp_f64(W, np.arange(n))
+    rt = 4 * 2.0 ** -24                      # paths have at most ~3 hops here
+    if not (np.abs(D32 - Dd) <= rt * Dd).all():
+        fails.append("continuous distances beyond float32 rounding")
+    B = P.bellman_first_hop(W, Dd)
+    diff = np.argwhere(N32 != B)
+    Wd = W.astype(np.float64)
+    for i, j in diff:
+        h = N32[i, j]
+        if h < 0 or i == j or abs(Wd[i, h] + Dd[h, j] - Dd[i, j]) > rt * Dd[i, j]:
+            fails.append(f"successor ({i}, {j}) = {h}, Bellman {B[i, j]}")
+            break
+    if len(diff) > n * n // 1000:
+        fails.append(f"{len(diff)} successors differ from the Bellman first hop")
+    if oracle.validate_walk(W, D32, N32, rtol=1e-6)[0] != 0:
+        fails.append("continuous walks")
+    return fails
+
+
 def test_hand_worked_fixture():
     W, Dg, NXg = P.load_golden(os.path.join(HERE, "golden", "hand_5.txt"))
     D, NX = oracle.fw_i32(W)
