@@ -7,8 +7,8 @@
  * dense n x n matrix whose entry (i, j) is the weight of edge i -> j, or
  * "infinite" for no edge; the output replaces it, in place, by the length of
  * a shortest path from i to j, and a second matrix records the paths.
- * Section 2.3 lists a reusable library for third-party C/C++ programs as the
- * paper's future work; this header is that library's interface.
+ * Section 5 (conclusions and future work) lists a reusable library for
+ * third-party C/C++ programs; this header is that library's interface.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -41,6 +41,11 @@
  *    per-device workspace (error word, schedule counters), so concurrent
  *    solves on different streams of one device must be serialised by the
  *    caller.
+ *  - Library-owned device memory is allocated on first use.  fw_init(device)
+ *    does that set-up ahead of time (error word, the lookahead's stream and
+ *    events, the allocation-free entry point's scratch address), so that a
+ *    later call can be captured in a hipGraph without an uncaptured call
+ *    first, as far as its own buffers are already large enough.
  */
 #ifndef FWGPU_FW_H
 #define FWGPU_FW_H
@@ -61,6 +66,11 @@ typedef enum fw_status {
 } fw_status;
 
 #define FW_INF_I32 1073741824   /* 2^30: int32 "no edge" and unreachable */
+
+/* Element types, for the entry point that takes the type as an argument. */
+#define FW_DTYPE_I32 0
+#define FW_DTYPE_F32 1
+#define FW_DTYPE_F64 2
 
 /* Schedules (fw_options.schedule). */
 #define FW_SCHED_AUTO 0         /* library's choice: three launches (or the
@@ -153,6 +163,38 @@ fw_status fw_solve_batched_f32(float *dist, int32_t *next, const int64_t *d_offs
                                int32_t batch, int32_t n_max, const fw_options *opt, void *stream);
 fw_status fw_solve_batched_f64(double *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
                                int32_t batch, int32_t n_max, const fw_options *opt, void *stream);
+
+/* Allocation-free batched solve: fw_solve_batched_* with the library's
+ * scratch taken from a fixed-size device array instead of device memory it
+ * allocates.  For callers that cannot allocate: code under hipGraph capture
+ * (including a first call), tight serving loops, and harnesses that forbid
+ * hipMalloc.  It never calls hipMalloc, hipFree or any other allocating
+ * routine.
+ *   dtype : FW_DTYPE_I32, FW_DTYPE_F32 or FW_DTYPE_F64; dist points to that
+ *           element type.
+ *   other arguments and results: as fw_solve_batched_*.
+ * Limit: the scratch holds 2^20 - 64 int32 (4 MiB per device, kept until the
+ * process ends); a batch whose order arrays and team flags need more --
+ * n_max + 2 batch + 67 ints for team 1, plus batch x (21 ceil(n_max/128) + 4,
+ * rounded up to 16) with teams -- returns FW_ERR_UNSUPPORTED with the sizes
+ * in fw_last_error() and enqueues nothing.  Its device error word is part of
+ * that array and is reported (and cleared) by fw_check like the others.
+ * Every call on one device uses the same array and leaves its contents
+ * behind (each call clears what must start at zero): calls that overlap on
+ * one device, on any streams, race and must be serialised by the caller.
+ * The array's address is resolved once per device (fw_init, else the first
+ * call on that device). */
+fw_status fw_solve_batched_static(int32_t dtype, void *dist, int32_t *next, const int64_t *d_offset,
+                                  const int32_t *d_n, int32_t batch, int32_t n_max, const fw_options *opt,
+                                  void *stream);
+
+/* Set-up of the library on `device` ahead of the first solve: the per-device
+ * workspace (error word), the three-launch lookahead's stream and events, and
+ * the allocation-free entry point's scratch address.  Restores the caller's
+ * current device; synchronises `device`.  Optional: every entry point does
+ * the part it needs on first use.  Errors: FW_ERR_INVALID_ARG for a device
+ * index outside [0, device count), FW_ERR_HIP. */
+fw_status fw_init(int device);
 
 /* Autotuners.  Each times its candidate configurations on the caller's own
  * input -- dist is copied to a scratch buffer first and restored before every

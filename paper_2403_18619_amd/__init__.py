@@ -5,13 +5,13 @@ hand-written HIP kernels; this package is its thin Python binding.
 """
 from ._binding import (FW_ERR_HIP, FW_ERR_INVALID_ARG, FW_ERR_NEGATIVE, FW_ERR_TIMEOUT,
                        FW_ERR_UNSUPPORTED, FLAG_EAGER_ARGMIN, FLAG_TEST_TIMEOUT, FLAG_TIME_PHASES, FW_INF_I32, FW_OK, LIB_PATH, PHASE_KINDS, SCHED_AUTO,
-                       SCHED_PERSISTENT, SCHED_THREE_LAUNCH, FwError, backward_, backward_batched_, check, tune_batched_, tune_solve_,
+                       SCHED_PERSISTENT, SCHED_THREE_LAUNCH, DTYPE_F32, DTYPE_F64, DTYPE_I32, FwError, backward_, backward_batched_, check, tune_batched_, tune_solve_,
                        header_symbols,
-                       last_error, lib, phase_times, solve, solve_, solve_batched_, status_string, version)
+                       init, last_error, lib, phase_times, solve, solve_, solve_batched_, status_string, version)
 
 from .autograd import FloydWarshall, shortest_paths
 
-__all__ = ["solve", "solve_", "solve_batched_", "backward_", "backward_batched_", "tune_solve_", "tune_batched_",
+__all__ = ["init", "solve", "solve_", "solve_batched_", "DTYPE_I32", "DTYPE_F32", "DTYPE_F64", "backward_", "backward_batched_", "tune_solve_", "tune_batched_",
            "FloydWarshall",
            "shortest_paths", "check", "phase_times", "FLAG_TIME_PHASES", "FLAG_EAGER_ARGMIN", "FLAG_TEST_TIMEOUT", "PHASE_KINDS", "FwError", "lib", "version", "status_string",
            "last_error", "header_symbols", "LIB_PATH", "FW_INF_I32", "SCHED_AUTO",

@@ -23,6 +23,7 @@ FW_ERR_TIMEOUT = -5
 FW_INF_I32 = 1 << 30
 
 SCHED_AUTO, SCHED_THREE_LAUNCH, SCHED_PERSISTENT = 0, 1, 2
+DTYPE_I32, DTYPE_F32, DTYPE_F64 = 0, 1, 2
 FLAG_TIME_PHASES = 1
 FLAG_EAGER_ARGMIN = 2
 FLAG_TEST_TIMEOUT = 4
@@ -62,6 +63,10 @@ def _load():
         f = getattr(lib, name)
         f.argtypes = [vp, vp, vp, vp, i32, i32, opt_p, vp]
         f.restype = i32
+    lib.fw_solve_batched_static.argtypes = [i32, vp, vp, vp, vp, i32, i32, opt_p, vp]
+    lib.fw_solve_batched_static.restype = i32
+    lib.fw_init.argtypes = [ctypes.c_int]
+    lib.fw_init.restype = i32
     lib.fw_backward_f32.argtypes = [vp, vp, vp, i64, i64, vp]
     lib.fw_backward_f32.restype = i32
     lib.fw_backward_batched_f32.argtypes = [vp, vp, vp, vp, vp, i32, i32, vp]
@@ -170,11 +175,18 @@ def solve(W, next_hop: bool = True, *, block: int = 0, schedule: int = 0,
     return D, NX
 
 
+def init(device: int = 0):
+    """Set up the library on a device ahead of the first solve (fw_init)."""
+    _raise_if(lib.fw_init(int(device)))
+
+
 def solve_batched_(dist, next, offsets, sizes, n_max: int, *, validate: bool = False,
-                   stream=None, flags: int = 0, team: int = 0):
+                   stream=None, flags: int = 0, team: int = 0, static: bool = False):
     """In-place batched solve.  dist / next: 1-D device arenas (int32 or
     float32 / int32); graph g is the sizes[g] x sizes[g] row-major block at
-    element offsets[g].  offsets (int64) and sizes (int32) are device tensors."""
+    element offsets[g].  offsets (int64) and sizes (int32) are device tensors.
+    static=True calls the allocation-free entry point
+    (fw_solve_batched_static) instead of fw_solve_batched_*."""
     import torch
     for t, name in ((dist, "dist"), (offsets, "offsets"), (sizes, "sizes")):
         if not t.is_cuda:
@@ -190,9 +202,14 @@ def solve_batched_(dist, next, offsets, sizes, n_max: int, *, validate: bool = F
     if next is not None and (next.dtype != torch.int32 or next.numel() < dist.numel()):
         raise ValueError("next must be an int32 arena at least as large as dist")
     opt = fw_options(0, 0, 1 if validate else 0, flags, team)
+    args = (dist.data_ptr(), None if next is None else next.data_ptr(), offsets.data_ptr(),
+            sizes.data_ptr(), sizes.numel(), int(n_max), ctypes.byref(opt), _stream_handle(stream))
     with torch.cuda.device(dist.device):
-        st = fn(dist.data_ptr(), None if next is None else next.data_ptr(), offsets.data_ptr(),
-                sizes.data_ptr(), sizes.numel(), int(n_max), ctypes.byref(opt), _stream_handle(stream))
+        if static:
+            dt = {torch.int32: DTYPE_I32, torch.float32: DTYPE_F32, torch.float64: DTYPE_F64}[dist.dtype]
+            st = lib.fw_solve_batched_static(dt, *args)
+        else:
+            st = fn(*args)
     _raise_if(st)
     return dist, next
 

@@ -310,8 +310,51 @@ int auto_team(fw::DType dt, bool next, int n_max) {
     return nt <= 2 ? 1 : 2 * nt;
 }
 
+// ---- allocation-free batched solve (fw_solve_batched_static): the
+// scratch is a file-scope device array, one copy per device, whose address
+// is resolved once per device (fw_init or the first call) and kept.  The
+// first kStaticErrInts ints hold the error word (padded to 256 bytes); the
+// batch layout follows.  Host code passes the resolved address, never the
+// array's name (a host-side stand-in, not a device address).
+constexpr int64_t kStaticScratchInts = int64_t(1) << 20;   // 4 MiB per device
+constexpr int64_t kStaticErrInts = 64;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) int scratch[kStaticScratchInts];
+std::mutex g_scratch_mu;
+int *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch` (resolved on first use).
+fw_status static_scratch(int **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(FW_ERR_UNSUPPORTED, "device %d (at most %d devices)", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int *p = nullptr;
+        e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(FW_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return FW_OK;
+}
+
+// Device error word of the allocation-free entry point on the current
+// device, or nullptr if that device's scratch was never resolved.
+int *static_err_word() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
+
+// Batched solve.  static_ws: scratch and error word come from the static
+// device array (nothing is allocated); otherwise from the per-device
+// workspace, grown on demand.
 fw_status solve_batched(fw::DType dt, void *dist, int32_t *next, const int64_t *d_offset, const int32_t *d_n,
-                        int32_t batch, int32_t n_max, const fw_options *opt, void *stream) {
+                        int32_t batch, int32_t n_max, const fw_options *opt, void *stream, bool static_ws = false) {
     g_err[0] = 0;
     if (batch < 0) return fail(FW_ERR_INVALID_ARG, "batch = %d is negative", batch);
     if (batch == 0) return FW_OK;
@@ -329,12 +372,25 @@ fw_status solve_batched(fw::DType dt, void *dist, int32_t *next, const int64_t *
         o = *opt;
     }
     const int team = o.team ? o.team : auto_team(dt, next != nullptr, n_max);
-    fw::DeviceWork *work = nullptr;
-    fw_status s = get_work(&work);
-    if (s != FW_OK) return s;
-    s = grow_ints(&work->batch, &work->batch_ints, fw::batched_workspace_ints(batch, n_max, team),
-                  "batch workspace");
-    if (s != FW_OK) return s;
+    const int64_t need = fw::batched_workspace_ints(batch, n_max, team);
+    int *sc = nullptr, *err = nullptr;
+    fw_status s;
+    if (static_ws) {
+        if (need > kStaticScratchInts - kStaticErrInts)
+            return fail(FW_ERR_UNSUPPORTED,
+                        "batch = %d, n_max = %d, team = %d needs %lld scratch ints; the allocation-free entry "
+                        "point has %lld (use fw_solve_batched_*, or a smaller batch or team)",
+                        batch, n_max, team, (long long)need, (long long)(kStaticScratchInts - kStaticErrInts));
+        if ((s = static_scratch(&sc)) != FW_OK) return s;
+        err = sc;
+        sc += kStaticErrInts;
+    } else {
+        fw::DeviceWork *work = nullptr;
+        if ((s = get_work(&work)) != FW_OK) return s;
+        if ((s = grow_ints(&work->batch, &work->batch_ints, need, "batch workspace")) != FW_OK) return s;
+        sc = work->batch;
+        err = work->err;
+    }
     fw::BatchPlan b;
     b.dtype = dt;
     b.dist = dist;
@@ -348,8 +404,8 @@ fw_status solve_batched(fw::DType dt, void *dist, int32_t *next, const int64_t *
     b.team_cap = team;
     s = wait_bound((o.flags & FW_FLAG_TEST_TIMEOUT) != 0, &b.timeout_ticks);
     if (s != FW_OK) return s;
-    b.scratch = work->batch;
-    b.err = work->err;
+    b.scratch = sc;
+    b.err = err;
     b.stream = (hipStream_t)stream;
     hipError_t e = fw::launch_batched(b);
     if (e != hipSuccess) return hip_fail(e, "batched launch");
@@ -643,6 +699,38 @@ fw_status fw_solve_ex_f32(float *dist, int32_t *next, int64_t n, int64_t ld,
     return solve(fw::DType::F32, dist, next, n, ld, opt, stream);
 }
 
+fw_status fw_init(int device) {
+    g_err[0] = 0;
+    int cur = 0, count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= count) return fail(FW_ERR_INVALID_ARG, "device = %d (%d devices)", device, count);
+    if ((e = hipGetDevice(&cur)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    fw::DeviceWork *w = nullptr;
+    int *sc = nullptr;
+    fw_status s = get_work(&w);
+    if (s == FW_OK) s = get_aux(w);
+    if (s == FW_OK) s = static_scratch(&sc);
+    if (s == FW_OK && (e = hipDeviceSynchronize()) != hipSuccess) s = hip_fail(e, "hipDeviceSynchronize");
+    if ((e = hipSetDevice(cur)) != hipSuccess && s == FW_OK) s = hip_fail(e, "hipSetDevice");
+    return s;
+}
+
+fw_status fw_solve_batched_static(int32_t dtype, void *dist, int32_t *next, const int64_t *d_offset,
+                                  const int32_t *d_n, int32_t batch, int32_t n_max, const fw_options *opt,
+                                  void *stream) {
+    g_err[0] = 0;
+    fw::DType dt;
+    switch (dtype) {
+    case FW_DTYPE_I32: dt = fw::DType::I32; break;
+    case FW_DTYPE_F32: dt = fw::DType::F32; break;
+    case FW_DTYPE_F64: dt = fw::DType::F64; break;
+    default: return fail(FW_ERR_INVALID_ARG, "dtype = %d", dtype);
+    }
+    return solve_batched(dt, dist, next, d_offset, d_n, batch, n_max, opt, stream, true);
+}
+
 fw_status fw_check(void *stream) {
     g_err[0] = 0;
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);
@@ -651,10 +739,19 @@ fw_status fw_check(void *stream) {
     fw_status s = get_work(&w);
     if (s != FW_OK) return s;
     int code = 0;
-    e = hipMemcpy(&code, w->err, sizeof code, hipMemcpyDeviceToHost);
+    int *werr = w->err;
+    e = hipMemcpy(&code, werr, sizeof code, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy(error word)");
+    if (code == 0) {
+        // the allocation-free entry point's error word, if that path ran here
+        if (int *se = static_err_word()) {
+            werr = se;
+            e = hipMemcpy(&code, werr, sizeof code, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpy(error word)");
+        }
+    }
     if (code == 0) return FW_OK;
-    e = hipMemset(w->err, 0, sizeof code);
+    e = hipMemset(werr, 0, sizeof code);
     if (e != hipSuccess) return hip_fail(e, "hipMemset(error word)");
     if (code == 1) return fail(FW_ERR_NEGATIVE, "a weight is negative or NaN");
     if (code == 2) return fail(FW_ERR_TIMEOUT, "a dependency wait exceeded its bound");
