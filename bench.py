@@ -14,10 +14,16 @@ Prints one JSON line.  Besides the driver's fields it carries
                  the solver's stream, against the MI355X VALU lane-op peak
                  (two operations per relaxation);
   cpu_baseline : the CPU oracle (plain triple loop) timed on this host on a
-                 bounded sample of the same recipe;
+                 bounded sample of the same recipe, on every core and on one;
+  dist_only    : the same graph solved for distances only;
+  plain_512    : n = 512, edge prob 0.5, int32 U[1,1000] (launch-bound:
+                 eager and captured steps);
+  dense_8192   : n = 8192 complete graph, float32 U[0,1), block size and
+                 schedule autotuned first;
   batched      : 4096 graphs, n ~ U{16..256}, edge prob 0.3, float32
                  U[0.1,10): one captured HIP graph (input restore + batched
-                 solve) per step, beside the same graphs solved one call each;
+                 solve) per step, beside the same graphs solved one call each
+                 (the calls captured in one HIP graph; the Python loop too);
   fwdbwd       : 64 complete graphs, n ~ U{64..1024}, float32 U[0.5,1.5),
                  N(0,1) upstream: autotuned batched forward, batched gradient
                  pass, beside per-graph forward solves.
@@ -82,28 +88,37 @@ def phase3_relaxations(n: int, bs: int) -> int:
 
 
 def cpu_baseline(args):
+    """The oracle as it is (plain triple loop, OpenMP over i within each k)
+    on this host: every core on a full n = cpu_n solve of the same recipe,
+    and one thread on a smaller one (n = cpu_n1)."""
     import oracle
     import synth
+
+    def recipe(m):
+        if args.dtype == "i32":
+            return synth.graph_i32(m, args.seed, args.p, int(args.lo), int(args.hi)), oracle.fw_i32
+        if args.dtype == "f32":
+            return synth.graph_f32(m, args.seed, args.p, args.lo, args.hi), oracle.fw_f32
+        return synth.graph_f32(m, args.seed, args.p, args.lo, args.hi).astype("float64"), oracle.fw_f64
+
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    m = args.cpu_n
-    if args.dtype == "i32":
-        W = synth.graph_i32(m, args.seed, args.p, args.lo, args.hi)
-        fn = oracle.fw_i32
-    elif args.dtype == "f32":
-        W = synth.graph_f32(m, args.seed, args.p, args.lo, args.hi)
-        fn = oracle.fw_f32
-    else:
-        W = synth.graph_f32(m, args.seed, args.p, args.lo, args.hi).astype("float64")
-        fn = oracle.fw_f64
-    log(f"cpu baseline: oracle on n={m}, {threads} threads")
-    t0 = time.perf_counter()
-    fn(W, next_hop=not args.no_next, nthreads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": m ** 3 / dt, "unit": "relaxations/s", "cores": threads, "kind": "oracle",
+    out = {}
+    for key, m, th in (("all", args.cpu_n, threads), ("one", args.cpu_n1, 1)):
+        W, fn = recipe(m)
+        log(f"cpu baseline: oracle on n={m}, {th} thread(s)")
+        t0 = time.perf_counter()
+        fn(W, next_hop=not args.no_next, nthreads=th)
+        out[key] = (m, th, time.perf_counter() - t0)
+    m, th, dt = out["all"]
+    m1, _, dt1 = out["one"]
+    what = "dist+next" if not args.no_next else "dist"
+    return {"value": m ** 3 / dt, "unit": "relaxations/s", "cores": th, "kind": "oracle",
             "sample": (f"plain triple-loop oracle, one full solve of the same recipe at n={m} "
-                       f"(seed {args.seed}), {'dist+next' if not args.no_next else 'dist'}, "
-                       f"{dt:.2f} s; rate scales as n^3 work"),
-            "seconds": dt}
+                       f"(seed {args.seed}), {what}, {dt:.2f} s on {th} threads; rate scales as n^3 work"),
+            "seconds": dt,
+            "one_thread": {"value": m1 ** 3 / dt1, "unit": "relaxations/s", "cores": 1,
+                           "sample": f"the same oracle, one full solve at n={m1}, {what}, {dt1:.2f} s",
+                           "seconds": dt1}}
 
 
 def _pack(sizes, gen):
@@ -127,8 +142,11 @@ def _time_graph(torch, graph, stream, reps):
     return a.elapsed_time(b) / reps
 
 
-def _per_graph_loop(torch, fw, Ws, next_hop=True):
-    """Plain per-graph method: one restore + fw_solve call per graph."""
+def _per_graph_loop(torch, fw, Ws, next_hop=True, reps=2):
+    """Plain per-graph method: one restore + fw_solve call per graph.
+    Returns (ms of the host loop from Python -- which includes the Python and
+    ctypes cost of every call --, ms of one replay of the same calls captured
+    in a HIP graph -- the kernels alone, launched one graph at a time)."""
     Ds = [torch.empty_like(w) for w in Ws]
     Ns = [torch.empty(w.shape, dtype=torch.int32, device=w.device) for w in Ws] if next_hop else [None] * len(Ws)
     for d, w, nx in zip(Ds, Ws, Ns):                   # warm-up: every size's workspace exists
@@ -141,7 +159,41 @@ def _per_graph_loop(torch, fw, Ws, next_hop=True):
         fw.solve_(d, nx)
     torch.cuda.synchronize()
     fw.check()
-    return (time.perf_counter() - t0) * 1e3
+    loop_ms = (time.perf_counter() - t0) * 1e3
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for d, w, nx in zip(Ds, Ws, Ns):
+            d.copy_(w)
+            fw.solve_(d, nx)
+    graph_ms = _time_graph(torch, g, torch.cuda.current_stream(), reps)
+    fw.check()
+    del g
+    return loop_ms, graph_ms
+
+
+def _time_call(torch, fn, reps):
+    """Mean ms of `reps` eager calls, HIP events on the current stream (the
+    stream the library launches on)."""
+    st = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(reps):
+        fn()
+    b.record(st)
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def _valu_roofline(relax, ms, what):
+    ops = OPS_PER_RELAX["f32"]
+    achieved = ops * relax / (ms / 1e3)
+    peak = VALU_PEAK_LANE_OPS["f32"]
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "Top/s",
+            "frac": achieved / peak, "traffic": None, "kernel": what, "avg_launch_ms": ms,
+            "ops_per_relaxation": ops}
 
 
 def bench_batched(torch, fw, synth, reps):
@@ -166,16 +218,23 @@ def bench_batched(torch, fw, synth, reps):
         fw.solve_batched_(D, NX, off, sz, 256)
     ms = _time_graph(torch, g, torch.cuda.current_stream(), reps)
     fw.check()
-    log(f"batched: {ms:.3f} ms per captured step (team {team})")
+    del g
+    call_ms = _time_call(torch, lambda: fw.solve_batched_(D, NX, off, sz, 256), reps)
+    fw.check()
+    log(f"batched: {ms:.3f} ms per captured step, {call_ms:.3f} ms per solve call (team {team})")
     Ws = [torch.from_numpy(synth.batch_graph_f32(n, i)).cuda() for i, n in enumerate(sizes)]
-    loop_ms = _per_graph_loop(torch, fw, Ws)
-    log(f"batched: per-graph loop {loop_ms:.1f} ms")
+    loop_ms, loop_graph_ms = _per_graph_loop(torch, fw, Ws)
+    log(f"batched: per-graph loop {loop_ms:.1f} ms from Python, {loop_graph_ms:.1f} ms as a captured graph")
     return {"workload": "4096 directed graphs, n ~ U{16..256}, edge prob 0.3, float32 U[0.1,10), dist + next",
             "graphs": len(sizes), "relaxations": relax, "ms_per_step": ms, "value": relax / (ms / 1e3),
             "unit": "relaxations/s", "team": team, "step": "one HIP graph replay: input restore + fw_solve_batched",
-            "per_graph_ms": loop_ms, "per_graph_value": relax / (loop_ms / 1e3),
-            "per_graph_step": "4096 x (restore + fw_solve_ex) calls from Python, one stream",
-            "speedup_vs_per_graph": loop_ms / ms}
+            "roofline": _valu_roofline(relax, call_ms, "fw_solve_batched (order, normalise, solve kernels)"),
+            "per_graph_ms": loop_graph_ms, "per_graph_value": relax / (loop_graph_ms / 1e3),
+            "per_graph_step": "4096 x (restore + fw_solve_ex) captured in one HIP graph, one stream",
+            "per_graph_python_loop_ms": loop_ms,
+            "per_graph_python_loop_note": "the same 4096 calls issued from Python: adds the Python and ctypes "
+                                          "cost of each call",
+            "speedup_vs_per_graph": loop_graph_ms / ms}
 
 
 def bench_fwdbwd(torch, fw, synth, reps):
@@ -210,19 +269,140 @@ def bench_fwdbwd(torch, fw, synth, reps):
     fwd_ms = _time_graph(torch, gf, st, reps)
     bwd_ms = _time_graph(torch, gb, st, reps)
     fw.check()
+    del gf, gb
+    fcall_ms = _time_call(torch, lambda: fw.solve_batched_(D, NX, off, sz, n_max), reps)
+    bcall_ms = _time_call(torch, lambda: fw.backward_batched_(G, NX, dW, off, sz, n_max), reps)
+    fw.check()
     log(f"fwdbwd: forward {fwd_ms:.3f} ms (team {team}), backward {bwd_ms:.3f} ms")
     Ws = [torch.from_numpy(synth.fwdbwd_graph_f32(n, i)).cuda() for i, n in enumerate(sizes)]
-    loop_ms = _per_graph_loop(torch, fw, Ws)
+    loop_ms, loop_graph_ms = _per_graph_loop(torch, fw, Ws)
     elems = float(sum(n * n for n in sizes))
+    # gradient pass: algorithmic bytes = read the upstream gradient and the
+    # successor matrix, write the weight gradient (12 B per entry); the
+    # two-pass kernels also write and read back one float per entry (24 B)
+    bwd_alg = 12.0 * elems
     return {"workload": "64 complete directed graphs, n ~ U{64..1024}, float32 U[0.5,1.5), upstream N(0,1)",
             "graphs": len(sizes), "relaxations": relax, "team": team,
             "forward_ms": fwd_ms, "backward_ms": bwd_ms, "total_ms": fwd_ms + bwd_ms,
             "forward_value": relax / (fwd_ms / 1e3), "unit": "relaxations/s",
             "fwdbwd_value": relax / ((fwd_ms + bwd_ms) / 1e3),
-            "backward_GBps": 16.0 * elems / (bwd_ms / 1e3) / 1e9,
-            "backward_bytes_per_element": 16,
-            "per_graph_forward_ms": loop_ms, "per_graph_forward_value": relax / (loop_ms / 1e3),
-            "speedup_forward_vs_per_graph": loop_ms / fwd_ms}
+            "forward_roofline": _valu_roofline(relax, fcall_ms, "fw_solve_batched (team schedule)"),
+            "backward_roofline": {"bound": "hbm", "achieved": bwd_alg / (bcall_ms / 1e3) / 1e9, "peak": 8000.0,
+                                  "unit": "GB/s", "frac": bwd_alg / (bcall_ms / 1e3) / 8e12, "traffic": None,
+                                  "kernel": "fw_backward_batched_f32 (two passes)", "avg_launch_ms": bcall_ms,
+                                  "bytes_per_entry": 12, "implementation_bytes_per_entry": 24},
+            "per_graph_forward_ms": loop_graph_ms, "per_graph_forward_value": relax / (loop_graph_ms / 1e3),
+            "per_graph_step": "64 x (restore + fw_solve_ex) captured in one HIP graph",
+            "per_graph_python_loop_ms": loop_ms,
+            "speedup_forward_vs_per_graph": loop_graph_ms / fwd_ms}
+
+
+PHASE_NOTE = ("per kind of launch, the summed durations of its launches (HIP events on the solve's streams); "
+              "the next round's phases 1-2 run on a second stream beside phase 3, so the kinds overlap "
+              "and their sum exceeds ms_per_step")
+
+
+def auto_block(n: int) -> int:
+    """The library's automatic block size for a single solve without a tuned
+    entry."""
+    return 32 if n <= 32 else 64 if n <= 64 else 128
+
+
+def measure_single(torch, fw, Wd, nx, dtype, steps, warmup, block=0, schedule=0, eff_block=None,
+                   traffic_key=None):
+    """Warm up, then time `steps` solves of Wd (distances, and successors
+    when nx is given), each after restoring the input: ms per step, the
+    roofline of the dominant kernel (phase 3, or the persistent kernel) and
+    the summed kernel time per kind of launch."""
+    n = Wd.shape[0]
+    bs = eff_block or block or auto_block(n)
+    stream = torch.cuda.current_stream()
+    D = torch.empty_like(Wd)
+
+    def step(flags):
+        D.copy_(Wd)
+        fw.solve_(D, nx, block=block, schedule=schedule, flags=flags, stream=stream)
+
+    log(f"n={n}: warmup x{warmup} ({'dist + next' if nx is not None else 'dist only'})")
+    for _ in range(warmup):
+        step(0)
+    torch.cuda.synchronize()
+    fw.check()
+    fw.phase_times()
+    log(f"n={n}: timing x{steps}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(fw.FLAG_TIME_PHASES)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fw.check()
+    ph = fw.phase_times()
+    ms = (t1 - t0) * 1e3 / steps
+    log(f"n={n}: {ms:.2f} ms/step, {n ** 3 / (ms / 1e3):.4g} relaxations/s")
+    kind = "persistent" if ph["persistent"][1] else "phase3"
+    k_ms, k_launches = ph[kind]
+    roofline = None
+    if k_launches:
+        relax_per_solve = phase3_relaxations(n, bs) if kind == "phase3" else n ** 3
+        relax_per_launch = relax_per_solve / (k_launches / steps)
+        avg_s = k_ms / k_launches / 1e3
+        ops = OPS_PER_RELAX[dtype]
+        achieved = ops * relax_per_launch / avg_s
+        peak = VALU_PEAK_LANE_OPS[dtype]
+        roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                    "unit": "Top/s", "frac": achieved / peak,
+                    "traffic": load_traffic(traffic_key) if traffic_key else None,
+                    "kernel": kind, "avg_launch_ms": avg_s * 1e3, "launches_per_step": k_launches / steps,
+                    "ops_per_relaxation": ops}
+    phase_ms = {k: (v[0] / steps) for k, v in ph.items() if v[1]}
+    del D
+    return ms, roofline, phase_ms
+
+
+def bench_plain_512(torch, fw, synth, steps):
+    """cfg1: one directed graph n = 512, edge prob 0.5, int32 U[1,1000],
+    distances + successors.  Launch-bound: timed as eager calls and as
+    one captured HIP graph (input restore + solve) per step."""
+    n = 512
+    Wd = torch.from_numpy(synth.plain_512()).cuda()
+    NX = torch.empty((n, n), dtype=torch.int32, device="cuda")
+    ms, roof, phase = measure_single(torch, fw, Wd, NX, "i32", steps, 10)
+    D = torch.empty_like(Wd)
+    g = torch.cuda.CUDAGraph()
+    D.copy_(Wd)
+    fw.solve_(D, NX)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        D.copy_(Wd)
+        fw.solve_(D, NX)
+    gms = _time_graph(torch, g, torch.cuda.current_stream(), steps)
+    fw.check()
+    del g
+    log(f"plain n=512: {ms:.3f} ms per eager step, {gms:.3f} ms per captured step")
+    return {"workload": "plain FW, one directed graph n=512, edge prob 0.5, int32 U[1,1000], INF 2^30, "
+                        "dist + next (seed 1)",
+            "n": n, "block": auto_block(n), "schedule": "auto (three launches)", "steps": steps,
+            "ms_per_step": ms, "value": n ** 3 / (ms / 1e3), "unit": "relaxations/s",
+            "captured_ms_per_step": gms, "captured_value": n ** 3 / (gms / 1e3),
+            "roofline": roof, "phase_kernel_ms_per_step": phase}
+
+
+def bench_dense_8192(torch, fw, synth, steps):
+    """cfg2: one complete directed graph n = 8192, float32 U[0,1), distances
+    + successors, block size and schedule autotuned on this input first."""
+    n = 8192
+    Wd = torch.from_numpy(synth.dense_f32(n)).cuda()
+    NX = torch.empty((n, n), dtype=torch.int32, device="cuda")
+    block, sched, tune_ms = fw.tune_solve_(Wd, NX, reps=2)
+    log(f"dense n=8192: tuned block {block}, schedule {sched} ({tune_ms:.1f} ms)")
+    ms, roof, phase = measure_single(torch, fw, Wd, NX, "f32", steps, 2, eff_block=block,
+                                     traffic_key=f"f32_n{n}_bs{block}_next")
+    return {"workload": "blocked FW, one complete directed graph n=8192, float32 U[0,1), dist + next (seed 2), "
+                        "block size and schedule autotuned",
+            "n": n, "block": block, "schedule": {1: "three-launch", 2: "persistent"}.get(sched, str(sched)),
+            "steps": steps, "ms_per_step": ms, "value": n ** 3 / (ms / 1e3), "unit": "relaxations/s",
+            "roofline": roof, "phase_kernel_ms_per_step": phase}
 
 
 def main():
@@ -240,8 +420,10 @@ def main():
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--no-next", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=8192)
+    ap.add_argument("--cpu-n1", type=int, default=2048, help="size of the one-thread oracle run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched and forward+backward lines")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the distances-only, n=512, n=8192, batched and forward+backward lines")
     ap.add_argument("--extra-reps", type=int, default=5)
     args = ap.parse_args()
 
@@ -267,70 +449,33 @@ def main():
     dev = torch.device("cuda:0")
     Wd = torch.from_numpy(W).to(dev)
     del W
-    D = torch.empty_like(Wd)
     NX = None if args.no_next else torch.empty((n, n), dtype=torch.int32, device=dev)
-    stream = torch.cuda.current_stream()
-    bs = args.block or 128
+    bs = args.block or auto_block(n)
 
-    def measure(nx, steps, warmup):
-        """Warm up, then time `steps` solves (distances, and successors when
-        nx is given): ms per step and the roofline of the dominant kernel."""
-        def step(flags):
-            D.copy_(Wd)
-            fw.solve_(D, nx, block=args.block, schedule=args.schedule, flags=flags, stream=stream)
+    def key(nx):
+        return f"{args.dtype}_n{n}_bs{bs}_{'next' if nx is not None else 'dist'}"
 
-        log(f"warmup x{warmup} ({'dist + next' if nx is not None else 'dist only'})")
-        for _ in range(warmup):
-            step(0)
-        torch.cuda.synchronize()
-        fw.check()
-        fw.phase_times()
-
-        log(f"timing x{steps}")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            step(fw.FLAG_TIME_PHASES)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        fw.check()
-        ph = fw.phase_times()
-        ms = (t1 - t0) * 1e3 / steps
-        log(f"{ms:.1f} ms/step, {n ** 3 / (ms / 1e3):.4g} relaxations/s")
-
-        # dominant kernel: phase 3 (or the persistent kernel)
-        kind = "persistent" if ph["persistent"][1] else "phase3"
-        k_ms, k_launches = ph[kind]
-        relax_per_solve = phase3_relaxations(n, bs) if kind == "phase3" else n ** 3
-        relax_per_launch = relax_per_solve / (k_launches / steps)
-        avg_s = k_ms / k_launches / 1e3
-        ops = OPS_PER_RELAX[args.dtype]
-        achieved = ops * relax_per_launch / avg_s
-        traffic = load_traffic(f"{args.dtype}_n{n}_bs{bs}_{'next' if nx is not None else 'dist'}")
-        peak = VALU_PEAK_LANE_OPS[args.dtype]
-        roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                    "unit": "Top/s", "frac": achieved / peak, "traffic": traffic,
-                    "kernel": kind, "avg_launch_ms": avg_s * 1e3, "launches_per_step": k_launches / steps,
-                    "ops_per_relaxation": ops}
-        phase_ms = {k: (v[0] / steps) for k, v in ph.items() if v[1]}
-        return ms, roofline, phase_ms
-
-    ms_per_step, roofline, phase_ms = measure(NX, args.steps, args.warmup)
+    ms_per_step, roofline, phase_ms = measure_single(torch, fw, Wd, NX, args.dtype, args.steps, args.warmup,
+                                                     args.block, args.schedule, traffic_key=key(NX))
     value = n ** 3 / (ms_per_step / 1e3)
 
     # the same graph for distances only, reported beside the primary result
     dist_only = None
     if NX is not None and not args.no_extras:
-        d_ms, d_roof, d_phase = measure(None, args.steps, 1)
+        d_ms, d_roof, d_phase = measure_single(torch, fw, Wd, None, args.dtype, args.steps, 1, args.block,
+                                               args.schedule, traffic_key=key(None))
         dist_only = {"workload": "the same graph, distances only (next = NULL)", "steps": args.steps,
                      "ms_per_step": d_ms, "value": n ** 3 / (d_ms / 1e3), "unit": "relaxations/s",
-                     "roofline": d_roof, "phase_ms_per_step": d_phase}
+                     "roofline": d_roof, "phase_kernel_ms_per_step": d_phase}
 
     has_next = NX is not None
-    del D, NX, Wd
+    del NX, Wd
     torch.cuda.empty_cache()
-    batched = fwdbwd = None
+    batched = fwdbwd = plain = dense = None
     if not args.no_extras:
+        plain = bench_plain_512(torch, fw, synth, 200)
+        dense = bench_dense_8192(torch, fw, synth, 10)
+        torch.cuda.empty_cache()
         batched = bench_batched(torch, fw, synth, args.extra_reps)
         fwdbwd = bench_fwdbwd(torch, fw, synth, args.extra_reps)
 
@@ -354,8 +499,11 @@ def main():
                    "next_hop": has_next, "seed": args.seed},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "phase_ms_per_step": phase_ms,
+        "phase_kernel_ms_per_step": phase_ms,
+        "phase_kernel_ms_note": PHASE_NOTE,
         "dist_only": dist_only,
+        "plain_512": plain,
+        "dense_8192": dense,
         "batched": batched,
         "fwdbwd": fwdbwd,
     }

@@ -78,3 +78,20 @@ def assert_next_unique_or_tied(W, D64, NXo, NXg, rtol=1e-5):
         alt = Wd[i, h] + D64[h, j]
         assert abs(alt - D64[i, j]) <= rtol * abs(D64[i, j]), (i, j, h, alt, D64[i, j])
     return len(diff)
+
+
+def pool_size():
+    """Worker threads for host-side checks: the machine's CPU share (16 per GPU)
+    or fewer where the machine has fewer cores."""
+    import os
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def oracle_many(graphs, fn=None):
+    """Float64 oracle distances of many small graphs, one OpenMP thread per
+    graph and a pool of host threads over the graphs (the C calls release
+    the GIL).  Returns the list of distance matrices."""
+    from concurrent.futures import ThreadPoolExecutor
+    fn = fn or (lambda W: oracle.fw_f64(W, next_hop=False, nthreads=1)[0])
+    with ThreadPoolExecutor(pool_size()) as ex:
+        return list(ex.map(fn, graphs))
