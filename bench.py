@@ -309,7 +309,7 @@ def auto_block(n: int) -> int:
 
 
 def measure_single(torch, fw, Wd, nx, dtype, steps, warmup, block=0, schedule=0, eff_block=None,
-                   traffic_key=None):
+                   traffic_key=None, flags=0):
     """Warm up, then time `steps` solves of Wd (distances, and successors
     when nx is given), each after restoring the input: ms per step, the
     roofline of the dominant kernel (phase 3, or the persistent kernel) and
@@ -319,9 +319,9 @@ def measure_single(torch, fw, Wd, nx, dtype, steps, warmup, block=0, schedule=0,
     stream = torch.cuda.current_stream()
     D = torch.empty_like(Wd)
 
-    def step(flags):
+    def step(timing):
         D.copy_(Wd)
-        fw.solve_(D, nx, block=block, schedule=schedule, flags=flags, stream=stream)
+        fw.solve_(D, nx, block=block, schedule=schedule, flags=flags | timing, stream=stream)
 
     log(f"n={n}: warmup x{warmup} ({'dist + next' if nx is not None else 'dist only'})")
     for _ in range(warmup):
@@ -419,6 +419,8 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--no-next", action="store_true")
+    ap.add_argument("--general-tile", action="store_true",
+                    help="three-launch phase 3 on the general tile (the persistent schedule's tile)")
     ap.add_argument("--cpu-n", type=int, default=8192)
     ap.add_argument("--cpu-n1", type=int, default=2048, help="size of the one-thread oracle run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -455,15 +457,16 @@ def main():
     def key(nx):
         return f"{args.dtype}_n{n}_bs{bs}_{'next' if nx is not None else 'dist'}"
 
+    gflag = fw.FLAG_GENERAL_TILE if args.general_tile else 0
     ms_per_step, roofline, phase_ms = measure_single(torch, fw, Wd, NX, args.dtype, args.steps, args.warmup,
-                                                     args.block, args.schedule, traffic_key=key(NX))
+                                                     args.block, args.schedule, traffic_key=key(NX), flags=gflag)
     value = n ** 3 / (ms_per_step / 1e3)
 
     # the same graph for distances only, reported beside the primary result
     dist_only = None
     if NX is not None and not args.no_extras:
         d_ms, d_roof, d_phase = measure_single(torch, fw, Wd, None, args.dtype, args.steps, 1, args.block,
-                                               args.schedule, traffic_key=key(None))
+                                               args.schedule, traffic_key=key(None), flags=gflag)
         dist_only = {"workload": "the same graph, distances only (next = NULL)", "steps": args.steps,
                      "ms_per_step": d_ms, "value": n ** 3 / (d_ms / 1e3), "unit": "relaxations/s",
                      "roofline": d_roof, "phase_kernel_ms_per_step": d_phase}
@@ -496,7 +499,7 @@ def main():
         "data": "synthetic (seeded counter-based generator)",
         "config": {"workload": wl, "n": n, "block": bs,
                    "schedule": {0: "auto", 1: "three-launch", 2: "persistent"}[args.schedule],
-                   "next_hop": has_next, "seed": args.seed},
+                   "general_tile": bool(args.general_tile), "next_hop": has_next, "seed": args.seed},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phase_kernel_ms_per_step": phase_ms,

@@ -108,6 +108,11 @@ typedef struct fw_options {
  * get a zero time bound, so a solve ends early with FW_ERR_TIMEOUT (reported
  * by fw_check) and unspecified output. */
 #define FW_FLAG_TEST_TIMEOUT 4
+/* fw_options.flags, measurements: the three-launch schedule's phase 3 runs
+ * the general tile -- the one the persistent schedule runs -- instead of the
+ * direct-copy tile, so that the two schedules can be compared with the same
+ * tile code.  Same results, bit for bit. */
+#define FW_FLAG_GENERAL_TILE 8
 
 /* Solve in place (Section 2.3, blocked form with block size BS).
  *   dist : n x n (storage n x ld) int32 / float32 weights in, distances out.

@@ -27,6 +27,7 @@ DTYPE_I32, DTYPE_F32, DTYPE_F64 = 0, 1, 2
 FLAG_TIME_PHASES = 1
 FLAG_EAGER_ARGMIN = 2
 FLAG_TEST_TIMEOUT = 4
+FLAG_GENERAL_TILE = 8
 PHASE_KINDS = ("init", "phase1", "phase2", "phase3", "persistent")
 
 

@@ -59,7 +59,8 @@ fw_status check_args(const void *dist, int64_t n, int64_t ld, const fw_options *
             return fail(FW_ERR_INVALID_ARG, "block = %d (allowed: 0, 32, 64, 128)", opt->block);
         if (opt->schedule < FW_SCHED_AUTO || opt->schedule > FW_SCHED_PERSISTENT)
             return fail(FW_ERR_INVALID_ARG, "schedule = %d", opt->schedule);
-        if (opt->flags & ~(FW_FLAG_TIME_PHASES | FW_FLAG_EAGER_ARGMIN | FW_FLAG_TEST_TIMEOUT)) return fail(FW_ERR_INVALID_ARG, "flags = %d (unknown bits)", opt->flags);
+        if (opt->flags & ~(FW_FLAG_TIME_PHASES | FW_FLAG_EAGER_ARGMIN | FW_FLAG_TEST_TIMEOUT | FW_FLAG_GENERAL_TILE))
+            return fail(FW_ERR_INVALID_ARG, "flags = %d (unknown bits)", opt->flags);
     }
     return FW_OK;
 }
@@ -205,6 +206,7 @@ fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
     p.vec = (ld % 4 == 0) && ((uintptr_t)dist % (4 * fw::dtype_bytes(dt)) == 0);   // 4-element vector accesses
     p.validate = o.validate != 0;
     p.eager_argmin = (o.flags & FW_FLAG_EAGER_ARGMIN) != 0;
+    p.general_tile = (o.flags & FW_FLAG_GENERAL_TILE) != 0;
     p.timeout_ticks = 0;
     p.stream = (hipStream_t)stream;
     s = get_work(&p.work);
@@ -223,7 +225,8 @@ fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
     }
     // the direct-copy phase 3 (block 128, aligned rows): int32 with successors
     // in packed keys, or 32-bit distances only
-    const bool direct = !persistent && p.bs == fw::kTile && p.vec && (packed || (!next && dt != fw::DType::F64));
+    const bool direct = !persistent && !p.general_tile && p.bs == fw::kTile && p.vec &&
+                        (packed || (!next && dt != fw::DType::F64));
     if (direct) {
         // operand panels (two parities, A' and B', 128 rows of 128 nt entries
         // each), fix-up counters (one per phase-3 launch) and tile list

@@ -42,6 +42,7 @@ struct Plan {
     bool vec;                  // 16-byte global accesses are legal
     bool validate;
     bool eager_argmin;         // successor variant: per-relaxation tracking
+    bool general_tile;         // three launches: phase 3 without the direct-copy tile
     uint64_t timeout_ticks;    // persistent schedule: wait bound (100 MHz ticks)
     hipStream_t stream;
     DeviceWork *work;

@@ -1724,7 +1724,8 @@ hipError_t minplus_t(const Plan &p, int K, int phase, int part) {
     constexpr bool PACKED = ARGMIN == 2 && std::is_same<U, uint32_t>::value;
     constexpr bool DIRECT = VEC && (PACKED || (ARGMIN == 0 && sizeof(U) == 4));
     int *bmax = PACKED ? p.work->bmax : nullptr;
-    uint32_t *panel = (DIRECT && p.bs == kTile) ? reinterpret_cast<uint32_t *>(p.work->panel) : nullptr;
+    uint32_t *panel = (DIRECT && p.bs == kTile && !p.general_tile) ? reinterpret_cast<uint32_t *>(p.work->panel)
+                                                                   : nullptr;
     const int64_t ppitch = (int64_t)p.nt * kTile;
     if constexpr (DIRECT) {
         if (phase == 3 && panel) {
