@@ -224,9 +224,11 @@ fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
         if (s != FW_OK) return s;
     }
     // the direct-copy phase 3 (block 128, aligned rows): int32 with successors
-    // in packed keys, or 32-bit distances only
+    // in packed keys, float32 with successors (chunk-end search), or 32-bit
+    // distances only
     const bool direct = !persistent && !p.general_tile && p.bs == fw::kTile && p.vec &&
-                        (packed || (!next && dt != fw::DType::F64));
+                        (packed || (!next && dt != fw::DType::F64) ||
+                         (next && dt == fw::DType::F32 && !p.eager_argmin));
     if (direct) {
         // operand panels (two parities, A' and B', 128 rows of 128 nt entries
         // each), fix-up counters (one per phase-3 launch) and tile list

@@ -59,15 +59,16 @@ template <> struct Arith<double> {
 };
 
 // Launch bounds.  Threads per workgroup of the min-plus code: 512 for the
-// deferred successor variant, else 256.  Minimum waves per SIMD: 32-bit
-// distances fit 128 VGPRs at four waves; 64-bit ones need twice the
-// registers and run two waves (one for the eager variant).
+// successor variants (8 x 4 entries per thread: a value and a chunk minimum,
+// or a value and an index, per entry), 256 for distances only (8 x 8).
+// Minimum waves per SIMD: 32-bit distances fit 128 VGPRs at four waves;
+// 64-bit ones need twice the registers and run two waves.
 template <typename U, int ARGMIN> struct Occ {
-    static constexpr int threads = ARGMIN == 2 ? 512 : 256;
+    static constexpr int threads = ARGMIN == 0 ? 256 : 512;
     // persistent and team kernels (the min-plus tile plus the schedule's own
     // state): the distances-only 8 x 8 patch runs three waves rather than spill
-    static constexpr int waves = sizeof(U) == 8 ? (ARGMIN == 1 ? 1 : 2) : (ARGMIN == 1 ? 1 : ARGMIN == 0 ? 3 : 4);
-    static constexpr int waves_standalone = sizeof(U) == 8 ? (ARGMIN == 2 ? 2 : 1) : (ARGMIN == 2 ? 4 : 1);
+    static constexpr int waves = sizeof(U) == 8 ? 2 : (ARGMIN == 0 ? 3 : 4);
+    static constexpr int waves_standalone = sizeof(U) == 8 ? (ARGMIN == 0 ? 1 : 2) : (ARGMIN == 0 ? 1 : 4);
 };
 
 // ------------------------------------------------------------------ init
@@ -260,6 +261,114 @@ __global__ __launch_bounds__(256) void phase1_kernel(U *__restrict__ D, int32_t 
     phase1_block<U, NEXT, BS, 256, false>(D, NX, n, ld, K, sm);
 }
 
+// Closure of a whole graph of n <= S vertices by one workgroup of NT threads
+// (the batched solve of small graphs: phase 1 with the graph as its block).
+// Thread (tx, ty) of an NT/16 x 16 grid keeps an MR x MC patch of the
+// distances and successors in registers (rows ty * MR + r, columns tx * MC +
+// c; MR = S / 16, MC = S * 16 / NT).  Step k reads row k and column k (and the
+// successors of column k) from double-buffered LDS vectors -- they do not
+// change during step k -- and the owners of row and column k + 1 publish
+// them; one barrier per step.  The k loop is not unrolled: the owners pick
+// the published registers through a switch on their static index.  Same
+// arithmetic, order and successor choice as phase1_block.
+template <typename U, bool NEXT, int S, int NT>
+__device__ __forceinline__ void closure_block(U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld,
+                                              Phase1Smem<U, S, false> &sm) {
+    constexpr int TX = NT / 16, MR = S / 16, MC = S / TX;
+    static_assert(MR * 16 == S && MC * TX == S && MR <= 8 && MC <= 4, "patch of at most 8 x 4");
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    const int tx = t % TX, ty = t / TX;
+    const int nn = (int)n;
+    U d[MR][MC];
+    int32_t nx[NEXT ? MR : 1][NEXT ? MC : 1];
+#pragma unroll
+    for (int r = 0; r < MR; ++r) {
+#pragma unroll
+        for (int c = 0; c < MC; ++c) {
+            const int li = ty * MR + r, lj = tx * MC + c;
+            const bool in = li < nn && lj < nn;
+            d[r][c] = in ? D[(int64_t)li * ld + lj] : ((li == lj) ? U(0) : Arith<U>::inf());
+            if (NEXT) nx[NEXT ? r : 0][NEXT ? c : 0] = in ? NX[(int64_t)li * ld + lj] : -1;
+        }
+    }
+    if (ty == 0) {
+#pragma unroll
+        for (int c = 0; c < MC; ++c) sm.rowb[0][tx * MC + c] = d[0][c];
+    }
+    if (tx == 0) {
+#pragma unroll
+        for (int r = 0; r < MR; ++r) {
+            sm.colb[0][ty * MR + r] = d[r][0];
+            if (NEXT) sm.nxb[0][ty * MR + r] = nx[NEXT ? r : 0][0];
+        }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int k = 0; k < nn; ++k) {
+        const int cur = k & 1;
+        U a[MR], b[MC];
+        int32_t na[MR];
+#pragma unroll
+        for (int r = 0; r < MR; ++r) {
+            a[r] = sm.colb[cur][ty * MR + r];
+            if (NEXT) na[r] = sm.nxb[cur][ty * MR + r];
+        }
+#pragma unroll
+        for (int c = 0; c < MC; ++c) b[c] = sm.rowb[cur][tx * MC + c];
+#pragma unroll
+        for (int r = 0; r < MR; ++r) {
+#pragma unroll
+            for (int c = 0; c < MC; ++c) {
+                const U sum = a[r] + b[c];
+                const bool lt = sum < d[r][c];
+                d[r][c] = lt ? sum : d[r][c];
+                if (NEXT) nx[NEXT ? r : 0][NEXT ? c : 0] = lt ? na[r] : nx[NEXT ? r : 0][NEXT ? c : 0];
+            }
+        }
+        const int k1 = k + 1;
+        if (k1 < nn) {
+            if (ty == k1 / MR) {                    // owner of row k + 1 (one wave)
+                switch (k1 % MR) {
+#define FW_PUB_ROW(R)                                                                 \
+    case R:                                                                           \
+        _Pragma("unroll") for (int c = 0; c < MC; ++c) sm.rowb[cur ^ 1][tx * MC + c] = \
+                d[(R) < MR ? (R) : 0][c];                                            \
+        break;
+                    FW_PUB_ROW(0) FW_PUB_ROW(1) FW_PUB_ROW(2) FW_PUB_ROW(3)
+                    FW_PUB_ROW(4) FW_PUB_ROW(5) FW_PUB_ROW(6) FW_PUB_ROW(7)
+#undef FW_PUB_ROW
+                }
+            }
+            if (tx == k1 / MC) {                    // owner of column k + 1
+                switch (k1 % MC) {
+#define FW_PUB_COL(C)                                                                            \
+    case C:                                                                                      \
+        _Pragma("unroll") for (int r = 0; r < MR; ++r) {                                        \
+            sm.colb[cur ^ 1][ty * MR + r] = d[r][(C) < MC ? (C) : 0];                           \
+            if (NEXT) sm.nxb[cur ^ 1][ty * MR + r] = nx[NEXT ? r : 0][NEXT && (C) < MC ? (C) : 0]; \
+        }                                                                                        \
+        break;
+                    FW_PUB_COL(0) FW_PUB_COL(1) FW_PUB_COL(2) FW_PUB_COL(3)
+#undef FW_PUB_COL
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < MR; ++r) {
+#pragma unroll
+        for (int c = 0; c < MC; ++c) {
+            const int li = ty * MR + r, lj = tx * MC + c;
+            if (li < nn && lj < nn) {
+                D[(int64_t)li * ld + lj] = d[r][c];
+                if (NEXT) NX[(int64_t)li * ld + lj] = nx[NEXT ? r : 0][NEXT ? c : 0];
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------- phases 2 and 3
 // Geometry of the 128 x 128 output tile.  Thread (tx, ty) of a TXN x 16 grid
 // owns 8 rows -- ty*4 + {0..3} and 64 + ty*4 + {0..3} -- and CPT columns --
@@ -354,7 +463,7 @@ __device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" 
 // and column band tile publishes the largest finite entry it holds (per round
 // parity) for the phase-3 tiles to test.
 template <typename U, int ARGMIN> struct alignas(4 * sizeof(U)) MinplusSmem {
-    static constexpr int NT = (ARGMIN == 2) ? 512 : 256;
+    static constexpr int NT = (ARGMIN == 0) ? 256 : 512;
     static constexpr int QCAP = 128;                           // queue entries per wave
     static constexpr int Q = (ARGMIN == 2) ? NT / 64 * QCAP : 1;
     // 64-bit entries are read as 32-byte vectors: declare that alignment (for
@@ -553,22 +662,32 @@ __device__ __forceinline__ void minplus_tile_impl(U *__restrict__ D, int32_t *__
                 }
             }
         } else if constexpr (ARGMIN == 1) {
+            // rows 64.. of the patch (r >= 4) exist only when the tile has
+            // more than 64 valid rows; a ragged tile (a small graph's last
+            // band) skips that half, uniformly across the workgroup (the k's
+            // past the band's end are INF operands and change nothing)
+            auto eager = [&](auto rows_t) {
+                constexpr int RR = decltype(rows_t)::value;
+                const int klim = (bk - kc < KC) ? bk - kc : KC;   // a short last band stops early
 #pragma unroll 2
-            for (int kk = 0; kk < KC; ++kk) {
-                U a[8], b[CPT];
-                lds_operands<U, NT>(As, Bs, kk, tx, ty, a, b);
-                const int kg = kc + kk;
+                for (int kk = 0; kk < klim; ++kk) {
+                    U a[8], b[CPT];
+                    lds_operands<U, NT>(As, Bs, kk, tx, ty, a, b);
+                    const int kg = kc + kk;
 #pragma unroll
-                for (int r = 0; r < 8; ++r) {
+                    for (int r = 0; r < RR; ++r) {
 #pragma unroll
-                    for (int c = 0; c < CPT; ++c) {
-                        const U s = a[r] + b[c];
-                        const bool lt = s < acc[r][c];
-                        acc[r][c] = lt ? s : acc[r][c];
-                        idx[r][c] = lt ? kg : idx[r][c];
+                        for (int c = 0; c < CPT; ++c) {
+                            const U s = a[r] + b[c];
+                            const bool lt = s < acc[r][c];
+                            acc[r][c] = lt ? s : acc[r][c];
+                            idx[r][c] = lt ? kg : idx[r][c];
+                        }
                     }
                 }
-            }
+            };
+            if (rows_valid > 64) eager(std::integral_constant<int, 8>{});
+            else eager(std::integral_constant<int, 4>{});
         } else if constexpr (ARGMIN == 0) {
 #pragma unroll 1
             for (int kk = 0; kk < KC; kk += 2) {
@@ -779,10 +898,10 @@ __device__ __forceinline__ void minplus_tile_impl(U *__restrict__ D, int32_t *__
             }
         }
     }
-    // ---- distances only (32-bit types): the band tiles write raw operand
-    // panels instead, same layout: B'[k][j] = D[b0 + k][j], A'[k][i] =
-    // D[i][b0 + k]
-    if constexpr (ARGMIN == 0 && sizeof(U) == 4) {
+    // ---- distances only (32-bit types), and float32 with deferred
+    // successors: the band tiles write raw operand panels instead, same
+    // layout: B'[k][j] = D[b0 + k][j], A'[k][i] = D[i][b0 + k]
+    if constexpr ((ARGMIN == 0 && sizeof(U) == 4) || (ARGMIN == 2 && std::is_same<U, float>::value)) {
         if (mode != 0 && panel) {
             uint32_t *const pa = panel + (int64_t)(K & 1) * 2 * kTile * ppitch;
 #pragma unroll
@@ -1166,6 +1285,246 @@ __global__ __launch_bounds__(256, 4) void minplus_direct_kernel(
     }
 }
 
+// ------------------- phase 3: direct-copy kernel, float32 with successors
+// Float sums carry no room for the improving k (the packed keys of int32),
+// so this tile keeps two minima per entry -- the running one, acc, and the
+// current chunk's, cm -- and finds the improving k only for the entries a
+// chunk strictly improves, while that chunk is still in LDS (the deferred
+// bookkeeping of the general tile, on the direct-copy operand path):
+//   - the band tiles write the round's raw operand panels (A'[k][i] k-major,
+//     B'[k][j]; round parity K & 1), and 16-k chunks of both are copied from
+//     memory straight into double-buffered LDS with global_load_lds;
+//   - 512 threads own 8 x 4 entries each (acc and cm: 64 VGPRs); per pair of
+//     k, two adds and one min3 per entry (in the compiler's order);
+//   - at each chunk's end the entries with cm < acc are queued per wave
+//     (ballot + mbcnt), folded into acc, and searched lane-parallel over the
+//     chunk's 16 k's for the first k with A'[k][i] + B'[k][j] == cm; the
+//     winner goes into an LDS byte matrix (one byte per entry);
+//   - afterwards the tile's block of the successor column band,
+//     next[i][b0 .. b0+127], is copied into the operand LDS in two halves and
+//     each improved entry takes next[i][b0 + k*]; only improved entries'
+//     successors are stored.
+// The chosen k is the first one (in increasing order) that reaches the final
+// minimum when that minimum beats the old value: the last strictly
+// improving chunk is the one that first reaches the final minimum, and the
+// search takes the first k in it -- the same k as every other variant.
+struct alignas(16) DirectSearchSmem {
+    static constexpr int NT = 512, WAVES = NT / 64, QCAP = 128;
+    float As[2][KCD][kTile];               // As[buf][k][i] = A'[chunk k][i]
+    float Bs[2][KCD][kTile];               // Bs[buf][k][j] = B'[chunk k][j]
+    uint32_t kst[kTile * kTile / 4];       // improving k per entry (bytes; 0xFF = none)
+    uint32_t qpos[WAVES * QCAP];           // queued entry: i | j << 8
+    float qval[WAVES * QCAP];              // its chunk minimum
+    int qmin[WAVES * 64];                  // per-entry search result
+};
+
+__global__ __launch_bounds__(512, 4) void minplus_direct_search_kernel(
+        float *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld, int K, int nt, int part,
+        const uint32_t *__restrict__ panel, int64_t ppitch, int *__restrict__ fix_count, int *__restrict__ fix_list) {
+    using SM = DirectSearchSmem;
+    __shared__ SM sm;
+    using G = Geo<512>;
+    constexpr int NT = SM::NT, QCAP = SM::QCAP;
+    const int64_t idx = phase3_tile(part, K, nt);
+    if (idx < 0) return;
+    const int64_t b0 = (int64_t)K * kTile;
+    const int64_t row0_ = (idx / nt) * kTile, col0_ = (idx % nt) * kTile;
+    if (row0_ == b0 || col0_ == b0) return;                       // the band's own tiles
+    if (!(n - b0 >= kTile && row0_ + kTile <= n && col0_ + kTile <= n && ld <= kFullTileMaxLd)) {
+        if (threadIdx.x == 0) fix_list[atomicAdd(fix_count, 1)] = (int)idx;
+        return;
+    }
+    const int64_t row0 = __builtin_amdgcn_readfirstlane((int)row0_);
+    const int64_t col0 = __builtin_amdgcn_readfirstlane((int)col0_);
+    const int64_t pitch = ld * 4;
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    const int tx = t % G::txn, ty = t / G::txn;
+    const int lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t pb = ppitch * 4;
+    const int64_t par = K & 1;
+    const char *const ap = reinterpret_cast<const char *>(panel + par * 2 * kTile * ppitch) + row0 * 4;
+    const char *const bp = reinterpret_cast<const char *>(panel + (par * 2 + 1) * kTile * ppitch) + col0 * 4;
+    // one global_load_lds of a wave moves two panel rows (lanes 0-31 row kr,
+    // lanes 32-63 row kr + 1); eight waves move a 16-row chunk of A' and B'
+    const uint32_t loff = (uint32_t)(lane >> 5) * (uint32_t)pb + (uint32_t)(lane & 31) * 16u;
+    auto copy_chunk = [&](int kc, int buf) {
+        const int kr = 2 * wv;
+        const int64_t go = (int64_t)(kc + kr) * pb;
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(ap + go + loff),
+                                         (__attribute__((address_space(3))) void *)&sm.As[buf][kr][0], 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(bp + go + loff),
+                                         (__attribute__((address_space(3))) void *)&sm.Bs[buf][kr][0], 16, 0, 0);
+    };
+    copy_chunk(0, 0);
+    for (int q = t; q < kTile * kTile / 4; q += NT) sm.kst[q] = 0xFFFFFFFFu;
+    for (int q = t; q < SM::WAVES * 64; q += NT) sm.qmin[q] = 0xFF;
+    // C, loaded before the k loop
+    const char *const cbase = reinterpret_cast<const char *>(D) + row0 * pitch + col0 * 4;
+    float acc[8][4];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const float4 v = *reinterpret_cast<const float4 *>(cbase + (int64_t)G::row_off(ty, r) * pitch +
+                                                           (int64_t)G::col_off(tx, 0) * 4);
+        acc[r][0] = v.x; acc[r][1] = v.y; acc[r][2] = v.z; acc[r][3] = v.w;
+    }
+    const int wq = wv * QCAP;           // this wave's queue
+    const int wq64 = wv * 64;           // this wave's search results
+    uint8_t *const kst8 = reinterpret_cast<uint8_t *>(sm.kst);
+#pragma unroll 1
+    for (int c = 0; c < kTile / KCD; ++c) {
+        wait_vmem();                               // this wave's copies of chunk c (and C)
+        __syncthreads();                           // everyone's; chunk c - 1 and its search are done
+        if (c + 1 < kTile / KCD) copy_chunk((c + 1) * KCD, (c + 1) & 1);
+        const float (*As)[kTile] = sm.As[c & 1];
+        const float (*Bs)[kTile] = sm.Bs[c & 1];
+        float cm[8][4];
+        {
+            float a[8], b[4], a2[8], b2[4];
+            lds_operands<float, 512, kTile>(As, Bs, 0, tx, ty, a, b);
+            lds_operands<float, 512, kTile>(As, Bs, 1, tx, ty, a2, b2);
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) cm[r][e] = __builtin_fminf(a[r] + b[e], a2[r] + b2[e]);
+        }
+#pragma unroll 1
+        for (int kk = 2; kk < KCD; kk += 2) {
+            float a[8], b[4], a2[8], b2[4];
+            lds_operands<float, 512, kTile>(As, Bs, kk, tx, ty, a, b);
+            lds_operands<float, 512, kTile>(As, Bs, kk + 1, tx, ty, a2, b2);
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    cm[r][e] = __builtin_fminf(cm[r][e], __builtin_fminf(a[r] + b[e], a2[r] + b2[e]));
+        }
+        // ---- strict improvements of this chunk: queue, fold, search
+        int txo = tx, tyo = ty;
+        asm volatile("" : "+v"(txo), "+v"(tyo));
+        const uint32_t ebase = (uint32_t)(tyo * 4) | ((uint32_t)(txo * 4) << 8);
+        bool again;
+        do {
+            int qcnt = 0;
+            again = false;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const bool imp = cm[r][e] < acc[r][e];
+                    const uint64_t m = __builtin_amdgcn_ballot_w64(imp);
+                    if (m) {                                     // uniform
+                        const int cnt = __builtin_popcountll(m);
+                        if (qcnt + cnt <= QCAP) {
+                            if (imp) {
+                                const int pos = qcnt + (int)__builtin_amdgcn_mbcnt_hi(
+                                                           (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                                sm.qpos[wq + pos] = ebase + (uint32_t)(G::row_off(0, r) | (G::col_off(0, e) << 8));
+                                sm.qval[wq + pos] = cm[r][e];
+                            }
+                            qcnt += cnt;
+                            acc[r][e] = __builtin_fminf(acc[r][e], cm[r][e]);
+                        } else {
+                            again = true;
+                        }
+                    }
+                }
+            }
+            // m entries per batch, L = 64 / m lanes each (a power of two, at
+            // most KCD); lane o of an entry scans k = o*span .. o*span+span-1
+            // and the entry's answer is the smallest hit over its lanes
+            for (int base = 0; base < qcnt; base += 64) {
+                const int m = (qcnt - base < 64) ? qcnt - base : 64;
+                wave_sync();
+                const int cl2 = (m <= 1) ? 0 : 32 - __builtin_clz((uint32_t)(m - 1));   // ceil(log2 m)
+                const int lg = (6 - cl2 < 4) ? 6 - cl2 : 4;                             // log2 L
+                const int span = KCD >> lg;
+                const int e = lane >> lg, o = lane & ((1 << lg) - 1);
+                int li = 0, lj = 0, kb = 0xFF;
+                if (e < m) {
+                    const uint32_t ent = sm.qpos[wq + base + e];
+                    li = (int)(ent & 0xFFu);
+                    lj = (int)(ent >> 8);
+                    const float tgt = sm.qval[wq + base + e];
+                    const int k0 = o * span;
+                    for (int q = span - 1; q >= 0; --q) kb = (As[k0 + q][li] + Bs[k0 + q][lj] == tgt) ? k0 + q : kb;
+                }
+                if (lg == 0) {
+                    if (e < m) kst8[li * kTile + lj] = (uint8_t)(c * KCD + kb);
+                } else {
+                    if (e < m && kb != 0xFF) atomicMin(&sm.qmin[wq64 + e], kb);
+                    wave_sync();
+                    if (e < m && o == 0) {
+                        kst8[li * kTile + lj] = (uint8_t)(c * KCD + sm.qmin[wq64 + e]);
+                        sm.qmin[wq64 + e] = 0xFF;
+                    }
+                }
+                wave_sync();
+            }
+        } while (again);
+    }
+    // ---- results: improving k per entry (0xFF: none)
+    __syncthreads();                               // every search's byte is in LDS
+    int txe = tx, tye = ty;
+    asm volatile("" : "+v"(txe), "+v"(tye));
+    uint32_t kw[8];
+    uint32_t any = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        kw[r] = sm.kst[(G::row_off(tye, r) * kTile + G::col_off(txe, 0)) >> 2];
+        any |= ~kw[r];                             // a byte other than 0xFF: improved
+    }
+    if (!__syncthreads_or(any != 0)) return;       // nothing improved: C is unchanged
+    char *const Db = reinterpret_cast<char *>(D);
+    char *const Nb = reinterpret_cast<char *>(NX);
+    int32_t (*const NXs)[kTile] = reinterpret_cast<int32_t (*)[kTile]>(&sm.As[0][0][0]);   // 64 rows, 32 KB
+    static_assert(sizeof(sm.As) + sizeof(sm.Bs) == 64 * kTile * sizeof(int32_t), "LDS for half the successor block");
+    const char *const nband = Nb + row0 * pitch + b0 * 4;
+    const uint32_t noff = (uint32_t)(lane >> 5) * (uint32_t)pitch + (uint32_t)(lane & 31) * 16u;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (h) __syncthreads();                    // the first half is consumed
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int x = 16 * q + 2 * wv;         // rows x, x + 1 of this half
+            __builtin_amdgcn_global_load_lds(
+                    (const __attribute__((address_space(1))) void *)(nband + (int64_t)(64 * h + x) * pitch + noff),
+                    (__attribute__((address_space(3))) void *)&NXs[x][0], 16, 0, 0);
+        }
+        wait_vmem();
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int r = 4 * h + rr;
+            const int li = G::row_off(tye, r);     // 64 h + local row
+            const int32_t *const nrow = NXs[li - 64 * h];
+            const int64_t ro = (row0 + li) * pitch;
+            const int64_t co = (col0 + G::col_off(txe, 0)) * 4;
+            float *dp = reinterpret_cast<float *>(Db + ro + co);
+            int32_t *np = reinterpret_cast<int32_t *>(Nb + ro + co);
+            uint32_t kb[4];
+            int32_t nxv[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                kb[e] = (kw[r] >> (8 * e)) & 0xFFu;
+                nxv[e] = nrow[kb[e] & 127u];       // k = 127 when unimproved (not stored)
+            }
+            const bool ch0 = kb[0] != 0xFFu, ch1 = kb[1] != 0xFFu, ch2 = kb[2] != 0xFFu, ch3 = kb[3] != 0xFFu;
+            if (ch0 || ch1 || ch2 || ch3)          // unimproved entries hold C itself
+                *reinterpret_cast<float4 *>(dp) = make_float4(acc[r][0], acc[r][1], acc[r][2], acc[r][3]);
+            if (ch0 && ch1 && ch2 && ch3) {
+                *reinterpret_cast<int4 *>(np) = make_int4(nxv[0], nxv[1], nxv[2], nxv[3]);
+            } else {
+                if (ch0) np[0] = nxv[0];
+                if (ch1) np[1] = nxv[1];
+                if (ch2) np[2] = nxv[2];
+                if (ch3) np[3] = nxv[3];
+            }
+        }
+    }
+}
+
 // The fix-up tiles of a direct-copy launch, with the general tile (packed
 // keys or not, ragged or not); a resident-size grid walks the list.
 template <typename U, int ARGMIN, bool VEC>
@@ -1469,7 +1828,8 @@ __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves))
 // largest graphs do not form the tail of the launch.
 template <typename U, int ARGMIN> union BatchSmem {
     MinplusSmem<U, ARGMIN> mp;
-    Phase1Smem<U, kTile, false> p1;
+    Phase1Smem<U, kTile, ARGMIN != 0> p1;      // successors in LDS: fewer registers
+    Phase1Smem<U, 64, false> small;            // graphs of at most 64 vertices
 };
 
 // Workgroups that may share one graph in the team schedule: every tile of
@@ -1624,7 +1984,7 @@ __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves))
 }
 
 template <typename U, int ARGMIN>
-__global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256) void batched_kernel(
+__global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (sizeof(U) == 4 && ARGMIN != 0 ? 4 : 1)) void batched_kernel(
         U *__restrict__ D, int32_t *__restrict__ NX, const int64_t *__restrict__ off,
         const int32_t *__restrict__ nv, const int *__restrict__ perm, int n_max, int validate,
         int *__restrict__ err) {
@@ -1649,12 +2009,22 @@ __global__ __launch_bounds__(ARGMIN == 2 ? 512 : 256) void batched_kernel(
     }
     if (validate && any_bad) atomicCAS(err, 0, 1);
     __syncthreads();
+    // at most 64 vertices (32-bit entries): the one-round solve by
+    // closure_block -- NT / 16 x 4 threads over a 64 x 64 block, 8 (or 16)
+    // entries each -- instead of phase1_block's 128 x 128 patch; same
+    // arithmetic, order and successor choice
+    if constexpr (sizeof(U) == 4) {
+        if (n <= 64) {
+            closure_block<U, NEXT, 64, NT>(Dg, NXg, n, n, sm.small);
+            return;
+        }
+    }
     const int R = (int)((n + BS - 1) / BS);
     const int nt = R;
     for (int K = 0; K < R; ++K) {
         const int64_t b0 = (int64_t)K * BS;
         const int64_t b1 = b0 + imin64((int64_t)BS, n - b0);
-        phase1_block<U, NEXT, BS, NT, false>(Dg, NXg, n, n, K, sm.p1);
+        phase1_block<U, NEXT, BS, NT, NEXT>(Dg, NXg, n, n, K, sm.p1);
         __syncthreads();
         if (R == 1) break;
         for (int q = 0; q < 2 * nt; ++q) {          // row band, then column band
@@ -1722,7 +2092,8 @@ hipError_t minplus_t(const Plan &p, int K, int phase, int part) {
     // the direct-copy phase 3 (block 128, aligned rows): int32 with
     // successors in packed keys, or 32-bit distances only
     constexpr bool PACKED = ARGMIN == 2 && std::is_same<U, uint32_t>::value;
-    constexpr bool DIRECT = VEC && (PACKED || (ARGMIN == 0 && sizeof(U) == 4));
+    constexpr bool SEARCH = ARGMIN == 2 && std::is_same<U, float>::value;   // float32 with successors
+    constexpr bool DIRECT = VEC && (PACKED || SEARCH || (ARGMIN == 0 && sizeof(U) == 4));
     int *bmax = PACKED ? p.work->bmax : nullptr;
     uint32_t *panel = (DIRECT && p.bs == kTile && !p.general_tile) ? reinterpret_cast<uint32_t *>(p.work->panel)
                                                                    : nullptr;
@@ -1734,8 +2105,13 @@ hipError_t minplus_t(const Plan &p, int K, int phase, int part) {
             const unsigned grid = part == 1 ? (unsigned)(2 * p.nt) : (unsigned)(8 * ((tiles + 7) / 8));
             int *cnt = p.work->fix + 2 * K + (part == 2 ? 1 : 0);
             int *list = p.work->fix + 2 * (int64_t)p.rounds;
-            hipLaunchKernelGGL((minplus_direct_kernel<U, PACKED>), dim3(grid), dim3(256), 0, p.stream, (U *)p.dist,
-                               p.next, p.n, p.ld, K, p.nt, bmax, part, panel, ppitch, cnt, list);
+            if constexpr (SEARCH) {
+                hipLaunchKernelGGL(minplus_direct_search_kernel, dim3(grid), dim3(512), 0, p.stream, (float *)p.dist,
+                                   p.next, p.n, p.ld, K, p.nt, part, panel, ppitch, cnt, list);
+            } else {
+                hipLaunchKernelGGL((minplus_direct_kernel<U, PACKED>), dim3(grid), dim3(256), 0, p.stream,
+                                   (U *)p.dist, p.next, p.n, p.ld, K, p.nt, bmax, part, panel, ppitch, cnt, list);
+            }
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
             const unsigned fgrid = (unsigned)imin64(part == 1 ? 2 * (int64_t)p.nt : tiles, 512);
@@ -1765,7 +2141,7 @@ hipError_t minplus_v(const Plan &p, int K, int phase, int part) {
 
 template <typename U, int ARGMIN, bool VEC>
 hipError_t persistent_t(const Plan &p) {
-    constexpr int NT = (ARGMIN == 2) ? 512 : 256;
+    constexpr int NT = Occ<U, ARGMIN>::threads;
     auto kern = persistent_kernel<U, ARGMIN, VEC>;
     static std::atomic<int> per_cu{0};
     int resident = 0;
@@ -1808,7 +2184,7 @@ BatchLayout batch_layout(int batch, int n_max, bool team) {
 
 template <typename U, int ARGMIN>
 hipError_t batched_t(const BatchPlan &b) {
-    constexpr int NT = (ARGMIN == 2) ? 512 : 256;
+    constexpr int NT = Occ<U, ARGMIN>::threads;
     const bool team = b.team_cap != 1;
     const BatchLayout L = batch_layout(b.batch, b.n_max, team);
     int *sc = b.scratch;
