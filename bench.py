@@ -297,6 +297,36 @@ def bench_fwdbwd(torch, fw, synth, reps):
             "speedup_forward_vs_per_graph": loop_graph_ms / fwd_ms}
 
 
+def profile_extras(torch, fw, synth):
+    """The batched (4096 graphs) and forward+backward (64 graphs) workloads
+    as plain calls on the current stream, one each after a warm-up call,
+    with the library's automatic team choice: a short, capture-free command
+    for counter profiles of their kernels."""
+    import numpy as np
+    for name, sizes, gen, ups in (
+            ("batched", [int(x) for x in synth.batch_sizes()], lambda n, g: synth.batch_graph_f32(n, g), None),
+            ("fwdbwd", [int(x) for x in synth.fwdbwd_sizes()], lambda n, g: synth.fwdbwd_graph_f32(n, g),
+             lambda n, g: synth.fwdbwd_upstream(n, g))):
+        n_max = max(sizes)
+        offs, arena = _pack(sizes, gen)
+        W0 = torch.from_numpy(arena).cuda()
+        D = torch.empty_like(W0)
+        NX = torch.empty(W0.numel(), dtype=torch.int32, device="cuda")
+        off = torch.from_numpy(offs).cuda()
+        sz = torch.from_numpy(np.asarray(sizes, np.int32)).cuda()
+        for _ in range(2):
+            D.copy_(W0)
+            fw.solve_batched_(D, NX, off, sz, n_max)
+        if ups is not None:
+            G = torch.from_numpy(_pack(sizes, ups)[1]).cuda()
+            dW = torch.empty_like(W0)
+            for _ in range(2):
+                fw.backward_batched_(G, NX, dW, off, sz, n_max)
+        torch.cuda.synchronize()
+        fw.check()
+        log(f"profile extras: {name} done")
+
+
 PHASE_NOTE = ("per kind of launch, the summed durations of its launches (HIP events on the solve's streams); "
               "the next round's phases 1-2 run on a second stream beside phase 3, so the kinds overlap "
               "and their sum exceeds ms_per_step")
@@ -427,6 +457,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the distances-only, n=512, n=8192, batched and forward+backward lines")
     ap.add_argument("--extra-reps", type=int, default=5)
+    ap.add_argument("--profile-extras", action="store_true",
+                    help="for counter profiles: only the batched and forward+backward solves, as plain calls "
+                         "(no autotuning, no HIP graphs, no per-graph loops), then exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -439,6 +472,10 @@ def main():
 
     import synth
     import paper_2403_18619_amd as fw
+
+    if args.profile_extras:
+        profile_extras(torch, fw, synth)
+        return
 
     n = args.n
     log(f"generating n={n} {args.dtype} graph (p={args.p}, U[{args.lo},{args.hi}], seed {args.seed})")

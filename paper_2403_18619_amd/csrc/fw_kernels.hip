@@ -261,8 +261,8 @@ __global__ __launch_bounds__(256) void phase1_kernel(U *__restrict__ D, int32_t 
     phase1_block<U, NEXT, BS, 256, false>(D, NX, n, ld, K, sm);
 }
 
-// Closure of a whole graph of n <= S vertices by one workgroup of NT threads
-// (the batched solve of small graphs: phase 1 with the graph as its block).
+// Closure of an n x n block (n <= S) by one workgroup of NT threads: phase 1
+// of the batched solve (a diagonal block, or a whole small graph).
 // Thread (tx, ty) of an NT/16 x 16 grid keeps an MR x MC patch of the
 // distances and successors in registers (rows ty * MR + r, columns tx * MC +
 // c; MR = S / 16, MC = S * 16 / NT).  Step k reads row k and column k (and the
@@ -275,7 +275,7 @@ template <typename U, bool NEXT, int S, int NT>
 __device__ __forceinline__ void closure_block(U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld,
                                               Phase1Smem<U, S, false> &sm) {
     constexpr int TX = NT / 16, MR = S / 16, MC = S / TX;
-    static_assert(MR * 16 == S && MC * TX == S && MR <= 8 && MC <= 4, "patch of at most 8 x 4");
+    static_assert(MR * 16 == S && MC * TX == S && MR <= 8 && MC <= 8, "patch of at most 8 x 8");
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));
     const int tx = t % TX, ty = t / TX;
@@ -350,6 +350,7 @@ __device__ __forceinline__ void closure_block(U *__restrict__ D, int32_t *__rest
         }                                                                                        \
         break;
                     FW_PUB_COL(0) FW_PUB_COL(1) FW_PUB_COL(2) FW_PUB_COL(3)
+                    FW_PUB_COL(4) FW_PUB_COL(5) FW_PUB_COL(6) FW_PUB_COL(7)
 #undef FW_PUB_COL
                 }
             }
@@ -1665,8 +1666,23 @@ __device__ __forceinline__ void p3_tile(int64_t q, int nxt, int nt, int &ti, int
 
 template <typename U, int ARGMIN> union PersistSmem {
     MinplusSmem<U, ARGMIN> mp;
-    Phase1Smem<U, kTile, ARGMIN != 0> p1;      // successors in LDS
+    Phase1Smem<U, kTile, false> p1c;                           // closure_block (32-bit)
+    Phase1Smem<U, kTile, ARGMIN != 0 && sizeof(U) == 8> p1;   // phase1_block, successors in LDS (64-bit)
 };
+
+// Phase 1 of round K on the diagonal block: 32-bit entries by closure_block
+// (successors in registers), 64-bit ones by phase1_block (successors in LDS);
+// the same bits either way.
+template <typename U, bool NEXT, int NT, typename SM>
+__device__ __forceinline__ void phase1_any(U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld,
+                                           int K, SM &sm) {
+    const int64_t b0 = (int64_t)K * kTile;
+    if constexpr (sizeof(U) == 4)
+        closure_block<U, NEXT, kTile, NT>(D + b0 * ld + b0, NEXT ? NX + b0 * ld + b0 : nullptr,
+                                          imin64(kTile, n - b0), ld, sm.p1c);
+    else
+        phase1_block<U, NEXT, kTile, NT, NEXT>(D, NX, n, ld, K, sm.p1);
+}
 
 // The whole solve of one graph by the workgroups that call it (every
 // workgroup of the persistent launch, or a team of the batched one).  Returns
@@ -1773,7 +1789,7 @@ __device__ __forceinline__ bool persistent_solve(U *__restrict__ D, int32_t *__r
             }
             // ---- the work
             if (item == 0)
-                phase1_block<U, NEXT, BS, NT, NEXT>(D, NX, n, ld, K, sm.p1);
+                phase1_any<U, NEXT, NT>(D, NX, n, ld, K, sm);
             else if (work)
                 minplus_tile<U, ARGMIN, VEC>(D, NX, n, ld, K, BS, mode, row0, col0, sm.mp,
                                              (ARGMIN == 2 && std::is_same<U, uint32_t>::value) ? ws.bmax : nullptr,
@@ -1828,7 +1844,8 @@ __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves))
 // largest graphs do not form the tail of the launch.
 template <typename U, int ARGMIN> union BatchSmem {
     MinplusSmem<U, ARGMIN> mp;
-    Phase1Smem<U, kTile, ARGMIN != 0> p1;      // successors in LDS: fewer registers
+    Phase1Smem<U, kTile, false> p1c;           // closure_block of a diagonal block (32-bit)
+    Phase1Smem<U, kTile, ARGMIN != 0 && sizeof(U) == 8> p1;   // phase1_block, successors in LDS (64-bit)
     Phase1Smem<U, 64, false> small;            // graphs of at most 64 vertices
 };
 
@@ -1974,7 +1991,7 @@ __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves))
         int32_t *NXg = NEXT ? NX + off[g] : nullptr;
         const int nt = (int)((n + kTile - 1) / kTile);
         if (nt == 1) {
-            phase1_block<U, NEXT, kTile, NT, NEXT>(Dg, NXg, n, n, 0, sm.p1);
+            phase1_any<U, NEXT, NT>(Dg, NXg, n, n, 0, sm);
             continue;
         }
         const PersistWs ws = persist_ws(wsbase + (int64_t)sg * ws_stride, nt, nt);
@@ -2024,7 +2041,7 @@ __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (sizeof(U) == 4 && ARGMI
     for (int K = 0; K < R; ++K) {
         const int64_t b0 = (int64_t)K * BS;
         const int64_t b1 = b0 + imin64((int64_t)BS, n - b0);
-        phase1_block<U, NEXT, BS, NT, NEXT>(Dg, NXg, n, n, K, sm.p1);
+        phase1_any<U, NEXT, NT>(Dg, NXg, n, n, K, sm);
         __syncthreads();
         if (R == 1) break;
         for (int q = 0; q < 2 * nt; ++q) {          // row band, then column band
