@@ -171,20 +171,25 @@ def _per_graph_loop(torch, fw, Ws, next_hop=True, reps=2):
     return loop_ms, graph_ms
 
 
-def _time_call(torch, fn, reps):
-    """Mean ms of `reps` eager calls, HIP events on the current stream (the
-    stream the library launches on)."""
+def _time_call(torch, fn, reps, pre=None):
+    """Mean ms of `reps` eager calls of `fn`, each bracketed by its own HIP
+    events on the current stream (the stream the library launches on);
+    `pre` (untimed) runs before each call, e.g. to restore the input so that
+    every timed solve starts from the same weights."""
     st = torch.cuda.current_stream()
+    if pre is not None:
+        pre()
     fn()
     torch.cuda.synchronize()
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record(st)
-    for _ in range(reps):
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        if pre is not None:
+            pre()
+        a.record(st)
         fn()
-    b.record(st)
-    b.synchronize()
-    return a.elapsed_time(b) / reps
+        b.record(st)
+    ev[-1][1].synchronize()
+    return sum(a.elapsed_time(b) for a, b in ev) / reps
 
 
 def _valu_roofline(relax, ms, what):
@@ -219,7 +224,7 @@ def bench_batched(torch, fw, synth, reps):
     ms = _time_graph(torch, g, torch.cuda.current_stream(), reps)
     fw.check()
     del g
-    call_ms = _time_call(torch, lambda: fw.solve_batched_(D, NX, off, sz, 256), reps)
+    call_ms = _time_call(torch, lambda: fw.solve_batched_(D, NX, off, sz, 256), reps, pre=lambda: D.copy_(W0))
     fw.check()
     log(f"batched: {ms:.3f} ms per captured step, {call_ms:.3f} ms per solve call (team {team})")
     Ws = [torch.from_numpy(synth.batch_graph_f32(n, i)).cuda() for i, n in enumerate(sizes)]
@@ -270,7 +275,7 @@ def bench_fwdbwd(torch, fw, synth, reps):
     bwd_ms = _time_graph(torch, gb, st, reps)
     fw.check()
     del gf, gb
-    fcall_ms = _time_call(torch, lambda: fw.solve_batched_(D, NX, off, sz, n_max), reps)
+    fcall_ms = _time_call(torch, lambda: fw.solve_batched_(D, NX, off, sz, n_max), reps, pre=lambda: D.copy_(W0))
     bcall_ms = _time_call(torch, lambda: fw.backward_batched_(G, NX, dW, off, sz, n_max), reps)
     fw.check()
     log(f"fwdbwd: forward {fwd_ms:.3f} ms (team {team}), backward {bwd_ms:.3f} ms")

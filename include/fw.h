@@ -98,7 +98,12 @@ typedef struct fw_options {
 
 /* fw_options.flags: record a pair of HIP events on the solve's stream around
  * every kernel launch and accumulate their durations per phase (read with
- * fw_phase_times).  The events are stream markers; the kernels are unchanged. */
+ * fw_phase_times).  The events are stream markers; the kernels are unchanged.
+ * (Internally, the three-launch schedule of an int32 solve with successors
+ * at block 128 first records, for an entry improved in a phase-3 tile, the
+ * vertex it improved through, and turns these tags into successors with one
+ * pass after the last round; that pass is timed with phase 3.  The tags never
+ * reach the caller.) */
 #define FW_FLAG_TIME_PHASES 1
 /* fw_options.flags: reference variant of the successor bookkeeping that
  * compares and records k at every relaxation (about 2.5x slower).  It selects
@@ -113,6 +118,10 @@ typedef struct fw_options {
  * direct-copy tile, so that the two schedules can be compared with the same
  * tile code.  Same results, bit for bit. */
 #define FW_FLAG_GENERAL_TILE 8
+/* fw_options.flags, tests only: an int32 solve with successors resolves its
+ * successor tags (see below) row by row in memory instead of staging each
+ * row in LDS -- the path rows longer than 32768 take.  Same results. */
+#define FW_FLAG_TEST_RESOLVE_MEMORY 16
 
 /* Solve in place (Section 2.3, blocked form with block size BS).
  *   dist : n x n (storage n x ld) int32 / float32 weights in, distances out.
@@ -281,7 +290,8 @@ fw_status fw_check(void *stream);
 
 /* Kernel time accumulated by solves run with FW_FLAG_TIME_PHASES since the
  * previous call, per kind of launch: index 0 input normalisation, 1 phase 1,
- * 2 phase 2, 3 phase 3, 4 persistent (whole solve).  Waits for the recorded
+ * 2 phase 2, 3 phase 3 (with its fix-up launches and the successor
+ * resolution pass), 4 persistent (whole solve).  Waits for the recorded
  * events, writes total milliseconds to ms[0..4] and launch counts to
  * launches[0..4] (host pointers, either may be NULL), then resets. */
 fw_status fw_phase_times(double *ms, int64_t *launches);

@@ -28,6 +28,7 @@ FLAG_TIME_PHASES = 1
 FLAG_EAGER_ARGMIN = 2
 FLAG_TEST_TIMEOUT = 4
 FLAG_GENERAL_TILE = 8
+FLAG_TEST_RESOLVE_MEMORY = 16
 PHASE_KINDS = ("init", "phase1", "phase2", "phase3", "persistent")
 
 

@@ -59,7 +59,8 @@ fw_status check_args(const void *dist, int64_t n, int64_t ld, const fw_options *
             return fail(FW_ERR_INVALID_ARG, "block = %d (allowed: 0, 32, 64, 128)", opt->block);
         if (opt->schedule < FW_SCHED_AUTO || opt->schedule > FW_SCHED_PERSISTENT)
             return fail(FW_ERR_INVALID_ARG, "schedule = %d", opt->schedule);
-        if (opt->flags & ~(FW_FLAG_TIME_PHASES | FW_FLAG_EAGER_ARGMIN | FW_FLAG_TEST_TIMEOUT | FW_FLAG_GENERAL_TILE))
+        if (opt->flags & ~(FW_FLAG_TIME_PHASES | FW_FLAG_EAGER_ARGMIN | FW_FLAG_TEST_TIMEOUT | FW_FLAG_GENERAL_TILE |
+                           FW_FLAG_TEST_RESOLVE_MEMORY))
             return fail(FW_ERR_INVALID_ARG, "flags = %d (unknown bits)", opt->flags);
     }
     return FW_OK;
@@ -207,6 +208,7 @@ fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
     p.validate = o.validate != 0;
     p.eager_argmin = (o.flags & FW_FLAG_EAGER_ARGMIN) != 0;
     p.general_tile = (o.flags & FW_FLAG_GENERAL_TILE) != 0;
+    p.resolve_in_memory = (o.flags & FW_FLAG_TEST_RESOLVE_MEMORY) != 0;
     p.timeout_ticks = 0;
     p.stream = (hipStream_t)stream;
     s = get_work(&p.work);
@@ -253,6 +255,11 @@ fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
     // caller's stream waits for them before round K+1's phase 3, so the solve
     // stays ordered on it (and a captured graph joins both streams).
     const bool ahead = p.bs == fw::kTile && p.rounds >= 3;
+    // The direct-copy phase 3 of an int32 solve with successors leaves
+    // successor tags (the improving vertex); one pass after the last round
+    // turns them into successors (timed with phase 3, whose bookkeeping it
+    // completes).
+    const bool tags = direct && packed;
     if (!ahead) {
         for (int K = 0; K < p.rounds; ++K) {
             e = timed(tm, 1, p.stream, [&] { return fw::launch_phase1(p, K); });
@@ -263,30 +270,34 @@ fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
             e = timed(tm, 3, p.stream, [&] { return fw::launch_phase3(p, K); });
             if (e != hipSuccess) return hip_fail(e, "phase 3 launch");
         }
-        return FW_OK;
-    }
-    s = get_aux(p.work);
-    if (s != FW_OK) return s;
-    fw::Plan q = p;
-    q.stream = p.work->aux;
-    e = timed(tm, 1, p.stream, [&] { return fw::launch_phase1(p, 0); });
-    if (e == hipSuccess) e = timed(tm, 2, p.stream, [&] { return fw::launch_phase2(p, 0); });
-    if (e != hipSuccess) return hip_fail(e, "phase 1/2 launch");
-    for (int K = 0; K < p.rounds; ++K) {
-        if (K + 1 == p.rounds) {
-            e = timed(tm, 3, p.stream, [&] { return fw::launch_phase3(p, K, 0); });
-            if (e != hipSuccess) return hip_fail(e, "phase 3 launch");
-            break;
+    } else {
+        s = get_aux(p.work);
+        if (s != FW_OK) return s;
+        fw::Plan q = p;
+        q.stream = p.work->aux;
+        e = timed(tm, 1, p.stream, [&] { return fw::launch_phase1(p, 0); });
+        if (e == hipSuccess) e = timed(tm, 2, p.stream, [&] { return fw::launch_phase2(p, 0); });
+        if (e != hipSuccess) return hip_fail(e, "phase 1/2 launch");
+        for (int K = 0; K < p.rounds; ++K) {
+            if (K + 1 == p.rounds) {
+                e = timed(tm, 3, p.stream, [&] { return fw::launch_phase3(p, K, 0); });
+                if (e != hipSuccess) return hip_fail(e, "phase 3 launch");
+                break;
+            }
+            e = timed(tm, 3, p.stream, [&] { return fw::launch_phase3(p, K, 1); });
+            if (e == hipSuccess) e = hipEventRecord(p.work->ev_a, p.stream);
+            if (e == hipSuccess) e = hipStreamWaitEvent(q.stream, p.work->ev_a, 0);
+            if (e == hipSuccess) e = timed(tm, 1, q.stream, [&] { return fw::launch_phase1(q, K + 1); });
+            if (e == hipSuccess) e = timed(tm, 2, q.stream, [&] { return fw::launch_phase2(q, K + 1); });
+            if (e == hipSuccess) e = hipEventRecord(p.work->ev_b, q.stream);
+            if (e == hipSuccess) e = timed(tm, 3, p.stream, [&] { return fw::launch_phase3(p, K, 2); });
+            if (e == hipSuccess) e = hipStreamWaitEvent(p.stream, p.work->ev_b, 0);
+            if (e != hipSuccess) return hip_fail(e, "lookahead round");
         }
-        e = timed(tm, 3, p.stream, [&] { return fw::launch_phase3(p, K, 1); });
-        if (e == hipSuccess) e = hipEventRecord(p.work->ev_a, p.stream);
-        if (e == hipSuccess) e = hipStreamWaitEvent(q.stream, p.work->ev_a, 0);
-        if (e == hipSuccess) e = timed(tm, 1, q.stream, [&] { return fw::launch_phase1(q, K + 1); });
-        if (e == hipSuccess) e = timed(tm, 2, q.stream, [&] { return fw::launch_phase2(q, K + 1); });
-        if (e == hipSuccess) e = hipEventRecord(p.work->ev_b, q.stream);
-        if (e == hipSuccess) e = timed(tm, 3, p.stream, [&] { return fw::launch_phase3(p, K, 2); });
-        if (e == hipSuccess) e = hipStreamWaitEvent(p.stream, p.work->ev_b, 0);
-        if (e != hipSuccess) return hip_fail(e, "lookahead round");
+    }
+    if (tags && p.rounds > 1) {
+        e = timed(tm, 3, p.stream, [&] { return fw::launch_resolve(p); });
+        if (e != hipSuccess) return hip_fail(e, "successor resolution launch");
     }
     return FW_OK;
 }

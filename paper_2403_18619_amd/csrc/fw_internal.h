@@ -43,6 +43,7 @@ struct Plan {
     bool validate;
     bool eager_argmin;         // successor variant: per-relaxation tracking
     bool general_tile;         // three launches: phase 3 without the direct-copy tile
+    bool resolve_in_memory;    // tests: successor resolution without the LDS row copy
     uint64_t timeout_ticks;    // persistent schedule: wait bound (100 MHz ticks)
     hipStream_t stream;
     DeviceWork *work;
@@ -93,6 +94,11 @@ hipError_t launch_phase2(const Plan &p, int K);
 // part 0: every phase-3 tile of round K; 1: the tiles of band K+1 only;
 // 2: all but those (block size 128)
 hipError_t launch_phase3(const Plan &p, int K, int part = 0);
+// after the last round of a solve whose direct-copy phase 3 stored
+// successor tags (int32 with successors): one workgroup per row turns them
+// into successors; rows of up to kResolveLdsMaxN entries are staged in LDS
+constexpr int kResolveLdsMaxN = 32768;
+hipError_t launch_resolve(const Plan &p);
 hipError_t launch_persistent(const Plan &p);
 int64_t persistent_workspace_ints(int rounds, int nt);
 hipError_t launch_batched(const BatchPlan &b);

@@ -38,6 +38,11 @@ namespace {
 constexpr int KC = 32;            // k-chunk staged in LDS per step
 constexpr int LDP = kTile + 4;    // LDS row pitch (elements), keeps 16-byte alignment
 constexpr uint32_t kInfU = 1u << 30;
+// A successor entry with bits 31..30 = 01 is a tag: "the successor of this
+// entry is that of entry (i, v & (kLazyBit - 1))" (direct-copy phase 3 of
+// int32 solves; resolve_next_kernel removes every tag before the solve ends).
+// Successors proper are -1 or below 2^30.
+constexpr int32_t kLazyBit = 1 << 30;
 
 __host__ __device__ __forceinline__ int64_t imin64(int64_t a, int64_t b) { return a < b ? a : b; }
 
@@ -1071,8 +1076,9 @@ __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves_s
 //     the rate of v_min3, and this order lets the two overlap (measured);
 //   - every global address is a per-tile base in scalar registers plus a
 //     per-thread offset, and there are no bounds or band tests; with
-//     successors, a tile none of whose entries improved skips the successor
-//     gather and the stores.
+//     successors, an improved entry records the improving vertex as a tag
+//     (resolve_next_kernel turns the tags into successors after the last
+//     round), so the tile reads nothing but its operands and C.
 // Same arithmetic, k order and results as the general tile.  A tile that does
 // not qualify is appended to the launch's fix-up list, which
 // minplus_fixup_kernel then runs with the general tile.
@@ -1196,19 +1202,6 @@ __global__ __launch_bounds__(256, 4) void minplus_direct_kernel(
         direct_chunk<U>(reinterpret_cast<const U (*)[kTile]>(sm.As[c & 1]),
                         reinterpret_cast<const U (*)[kTile]>(sm.Bs[c & 1]), tx, ty, acc);
     }
-    if constexpr (PACKED) {
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int64_t ro = (int64_t)G::row_off(ty, r) * pitch;
-#pragma unroll
-            for (int g = 0; g < 2; ++g) {
-                const uint4 v = *reinterpret_cast<const uint4 *>(cbase + ro + (int64_t)G::col_off(tx, 4 * g) * 4);
-                const uint32_t w[4] = {pack_a(v.x), pack_a(v.y), pack_a(v.z), pack_a(v.w)};
-#pragma unroll
-                for (int e = 0; e < 4; ++e) acc[r][4 * g + e] = Arith<U>::mn(acc[r][4 * g + e], w[e]);
-            }
-        }
-    }
     if constexpr (!PACKED) {
         // distances only: the tile's new values, four at a time
         char *const Db = reinterpret_cast<char *>(D);
@@ -1223,65 +1216,74 @@ __global__ __launch_bounds__(256, 4) void minplus_direct_kernel(
             }
         }
     } else {
-        // Keys -> results: bit 0 = improved, bits 1..7 = k, bits 8.. = value.
-        // The successor of an improved entry is A's, NX[i][b0 + k] (the
-        // column band is not written during phase 3).  That 128 x 128 block
-        // of NX is copied into the LDS the operands no longer need, 64 rows at
-        // a time (the same direct-to-LDS copy), and gathered from there.  Only
-        // improved entries are stored, four at once only when all four
-        // improved (an unimproved key holds min(C, S), not C).  The barrier
-        // that ends the operand reads also tells whether any entry of the
-        // tile improved; if none did, the workgroup is done.
-        uint32_t any = 0;
-#pragma unroll
-        for (int r = 0; r < 8; ++r)
-#pragma unroll
-            for (int c = 0; c < 8; ++c) any |= acc[r][c];
-        if (!__syncthreads_or((int)(any & 1u))) return;
+        // C's keys are folded in two rows at a time, the next two rows'
+        // loads issued before this pair's stores (empty asm statements keep
+        // the compiler from hoisting every load, which would spill).  Keys ->
+        // results:
+        // bit 0 = improved, bits 1..7 = k, bits 8.. = value.  An improved
+        // entry stores its new distance and, in place of its successor, the
+        // tag of the improving vertex b0 + k (its successor is that of entry
+        // (i, b0 + k), looked up once the solve has ended:
+        // resolve_next_kernel).  Only improved entries are stored, four at
+        // once only when all four improved (an unimproved key holds
+        // min(C, S), not C).
         char *const Db = reinterpret_cast<char *>(D);
         char *const Nb = reinterpret_cast<char *>(NX);
-        int32_t (*const NXs)[kTile] = reinterpret_cast<int32_t (*)[kTile]>(&sm);   // 64 rows, 32 KB
-        static_assert(sizeof(DirectSmem) == 64 * kTile * sizeof(int32_t), "LDS for half the successor block");
-        const char *const nband = Nb + row0 * pitch + b0 * 4;
-        const uint32_t noff = (uint32_t)(lane >> 5) * (uint32_t)pitch + (uint32_t)(lane & 31) * 16u;
+        const int32_t tag0 = kLazyBit | (int32_t)b0;
+        uint4 cv[2][2][2];                         // [buffer][row][half row]
+        auto load_c = [&](int h) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            if (h) __syncthreads();                // the first half is consumed
+            for (int rr = 0; rr < 2; ++rr)
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int x = 8 * q + 2 * wv;      // rows x, x + 1 of this half
-                __builtin_amdgcn_global_load_lds(
-                        (const __attribute__((address_space(1))) void *)(nband + (int64_t)(64 * h + x) * pitch + noff),
-                        (__attribute__((address_space(3))) void *)&NXs[x][0], 16, 0, 0);
-            }
-            wait_vmem();
-            __syncthreads();
+                for (int g = 0; g < 2; ++g)
+                    cv[h & 1][rr][g] = *reinterpret_cast<const uint4 *>(
+                            cbase + (int64_t)G::row_off(ty, 2 * h + rr) * pitch + (int64_t)G::col_off(tx, 4 * g) * 4);
+        };
+        auto fold_c = [&](int h) {
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int r = 4 * h + rr;
-                const int li = G::row_off(ty, r);  // 64 h + local row
-                const int32_t *const nrow = NXs[li - 64 * h];
-                const int64_t ro = (row0 + li) * pitch;
+            for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+                for (int g = 0; g < 2; ++g) {
+                    const uint4 &c = cv[h & 1][rr][g];
+                    uint32_t *const e = &acc[2 * h + rr][4 * g];
+                    e[0] = Arith<U>::mn(e[0], pack_a(c.x)); e[1] = Arith<U>::mn(e[1], pack_a(c.y));
+                    e[2] = Arith<U>::mn(e[2], pack_a(c.z)); e[3] = Arith<U>::mn(e[3], pack_a(c.w));
+                }
+        };
+        auto store = [&](int h) {
+#pragma unroll
+            for (int rr = 0; rr < 2; ++rr) {
+                const int r = 2 * h + rr;
+                const int64_t ro = (row0 + G::row_off(ty, r)) * pitch;
 #pragma unroll
                 for (int g = 0; g < 2; ++g) {
                     const int64_t co = (col0 + G::col_off(tx, 4 * g)) * 4;
                     uint32_t *dp = reinterpret_cast<uint32_t *>(Db + ro + co);
                     int32_t *np = reinterpret_cast<int32_t *>(Nb + ro + co);
                     const uint32_t *e = &acc[r][4 * g];
-                    int32_t nxv[4];
+                    int32_t tag[4];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) nxv[q] = nrow[(e[q] >> 1) & 127u];   // k = 0 when unimproved
+                    for (int q = 0; q < 4; ++q) tag[q] = tag0 + (int32_t)((e[q] >> 1) & 127u);
                     const bool all = (e[0] & e[1] & e[2] & e[3] & 1u) != 0;
                     if (all) {
                         *reinterpret_cast<uint4 *>(dp) = make_uint4(e[0] >> 8, e[1] >> 8, e[2] >> 8, e[3] >> 8);
-                        *reinterpret_cast<int4 *>(np) = make_int4(nxv[0], nxv[1], nxv[2], nxv[3]);
+                        *reinterpret_cast<int4 *>(np) = make_int4(tag[0], tag[1], tag[2], tag[3]);
                     } else {
 #pragma unroll
                         for (int q = 0; q < 4; ++q)
-                            if (e[q] & 1u) { dp[q] = e[q] >> 8; np[q] = nxv[q]; }
+                            if (e[q] & 1u) { dp[q] = e[q] >> 8; np[q] = tag[q]; }
                     }
                 }
             }
+        };
+        load_c(0);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            fold_c(h);
+            if (h + 1 < 4) load_c(h + 1);
+            asm volatile("" ::: "memory");
+            store(h);
+            asm volatile("" ::: "memory");
         }
     }
 }
@@ -1541,6 +1543,74 @@ minplus_fixup_kernel(U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int
         if (band_tile(0, fix_list[q], n, b0, b1, nt, row0, col0))
             minplus_tile<U, ARGMIN, VEC>(D, NX, n, ld, K, kTile, 0, row0, col0, sm, bmax, nt);
         __syncthreads();                           // LDS is reused by the next tile
+    }
+}
+
+// ------------------------------------------------ successor resolution
+// After the last round of a three-launch int32 solve with successors, entries
+// the direct-copy phase 3 improved hold tags (kLazyBit | k: "successor of
+// (i, j) = successor of (i, k)", k the improving vertex).  The final
+// successors follow from the final matrix: when a relaxation through k gave
+// (i, j) its final distance, d(i, k) was already final -- had it dropped
+// later, d(i, k) + d(k, j) would undercut the final d(i, j), which with
+// integer sums is the exact shortest distance -- and a successor changes only
+// with a strict decrease of its own distance, so the successor the eager
+// bookkeeping copies at that moment is the final successor of (i, k).  A tag
+// names an entry last written before the tag was, so the tags of a row form
+// chains without cycles that end at successors.  One workgroup per row
+// resolves them by pointer jumping (a tag takes the value of the entry it
+// names; after p passes a chain of length below 2^p is resolved): one or two
+// passes on the dense graphs of the measurements.  Rows of at most CAP
+// entries are staged in LDS and written back whole if they held a tag; CAP =
+// 0 works on the row in memory.  Input that breaks the contract (a negative
+// cycle) could make a cycle of tags: the passes stop after kResolvePasses
+// (chains are shorter than 2^31) and a tag still left, or one naming an
+// entry outside the row, becomes -1.
+constexpr int kResolveThreads = 1024;
+constexpr int kResolvePasses = 40;
+__device__ __forceinline__ bool is_tag(int32_t v) { return (v & (int32_t)0xC0000000) == kLazyBit; }
+__device__ __forceinline__ int32_t ld_wg(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void st_wg(int32_t *p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <int CAP>
+__global__ __launch_bounds__(kResolveThreads) void resolve_next_kernel(int32_t *__restrict__ NX, int64_t n,
+                                                                       int64_t ld) {
+    __shared__ int32_t row[CAP > 0 ? CAP : 1];
+    const int t = threadIdx.x;
+    int32_t *const g = NX + (int64_t)blockIdx.x * ld;
+    int32_t *const r = CAP > 0 ? row : g;
+    bool any = false;
+#pragma unroll 8
+    for (int64_t j = t; j < n; j += kResolveThreads) {
+        const int32_t v = g[j];
+        if (CAP > 0) row[j] = v;
+        any |= is_tag(v);
+    }
+    if (!__syncthreads_or(any)) return;            // no tag in this row
+    bool left = true;
+    for (int pass = 0; pass < kResolvePasses && left; ++pass) {
+        bool l = false;
+        for (int64_t j = t; j < n; j += kResolveThreads) {
+            const int32_t v = ld_wg(r + j);
+            if (is_tag(v)) {
+                const int32_t k = v & (kLazyBit - 1);
+                const int32_t w = k < n ? ld_wg(r + k) : -1;
+                st_wg(r + j, w);
+                l |= is_tag(w);
+            }
+        }
+        __syncthreads();                           // this pass's values are visible to the next
+        left = __syncthreads_or(l);
+    }
+#pragma unroll 8
+    for (int64_t j = t; j < n; j += kResolveThreads) {
+        const int32_t v = r[j];
+        if (CAP > 0) g[j] = is_tag(v) ? -1 : v;
+        else if (is_tag(v)) g[j] = -1;
     }
 }
 
@@ -2302,6 +2372,18 @@ hipError_t launch_phase2(const Plan &p, int K) {
     case DType::F32: return minplus_dispatch<float>(p, K, 2, 0);
     default: return minplus_dispatch<double>(p, K, 2, 0);
     }
+}
+
+hipError_t launch_resolve(const Plan &p) {
+    if (!p.next || p.n == 0) return hipSuccess;
+    const dim3 grid((unsigned)p.n), block(kResolveThreads);
+    if (!p.resolve_in_memory && p.n <= 4096)
+        hipLaunchKernelGGL(resolve_next_kernel<4096>, grid, block, 0, p.stream, p.next, p.n, p.ld);
+    else if (!p.resolve_in_memory && p.n <= kResolveLdsMaxN)
+        hipLaunchKernelGGL(resolve_next_kernel<kResolveLdsMaxN>, grid, block, 0, p.stream, p.next, p.n, p.ld);
+    else
+        hipLaunchKernelGGL(resolve_next_kernel<0>, grid, block, 0, p.stream, p.next, p.n, p.ld);
+    return hipGetLastError();
 }
 
 hipError_t launch_phase3(const Plan &p, int K, int part) {

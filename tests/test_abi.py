@@ -47,7 +47,7 @@ def test_invalid_arguments_rejected_on_host(fn):
 def test_invalid_options_rejected_on_host(fn):
     f = getattr(fw.lib, fn)
     for opt in (B.fw_options(48, 0, 0, 0), B.fw_options(256, 0, 0, 0), B.fw_options(0, 7, 0, 0),
-                B.fw_options(0, -1, 0, 0), B.fw_options(0, 0, 0, 16)):
+                B.fw_options(0, -1, 0, 0), B.fw_options(0, 0, 0, 32)):
         assert f(FAKE, None, 16, 16, ctypes.byref(opt), None) == fw.FW_ERR_INVALID_ARG
         assert fw.last_error()
     # a valid request the persistent schedule does not run: refused on the host

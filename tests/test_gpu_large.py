@@ -8,7 +8,9 @@ times (default block size and schedule).
   - n = 32768 headline graph: Dijkstra from 64 seeded random sources plus
     rows 0 and n-1, bit-exact, walks and triangle inequality on them.
 The two larger cases also solve for distances only (a phase 3 of its own)
-and require the same bits as the solve with successors.
+and require the same bits as the solve with successors.  The int32 solves
+at n = 32768 and 32896 (rows resolved in LDS / in memory after the last
+round) also match the eager successor bookkeeping bit for bit.
 """
 import numpy as np
 import pytest
@@ -73,6 +75,10 @@ def test_headline_n32768_sampled_rows():
     Dd, _ = _solve_device(W, next_hop=False)
     assert torch_equal(D, Dd)
     del Dd
+    import paper_2403_18619_amd as fw
+    _, Nm = _solve_device(W, flags=fw.FLAG_TEST_RESOLVE_MEMORY)
+    assert torch_equal(NX, Nm)
+    del Nm
     # walks on the sampled rows need the full successor matrix on the host
     Dh, NXh = D.cpu().numpy(), NX.cpu().numpy()
     del D, NX
@@ -83,6 +89,25 @@ def test_headline_n32768_sampled_rows():
     for k in ks:
         assert (Di <= Di[:, k:k + 1] + Dh[k].astype(np.int64)[None, :]).all()
     assert (Dh[rows] <= np.where(W[rows] >= INF, INF, W[rows])).all()        # D <= W
+
+
+def test_headline_recipe_n32896_rows_in_memory():
+    """Rows longer than 32768 entries: the successor tags are resolved in
+    memory.  Same bits as the eager bookkeeping; Dijkstra rows, walks."""
+    log("case headline recipe n=32896")
+    import paper_2403_18619_amd as fw
+    n = 32896
+    W = synth.graph_i32(n, 3, 0.8, 1, 10000)
+    D, NX = _solve_device(W)
+    _, Ne = _solve_device(W, flags=fw.FLAG_EAGER_ARGMIN)
+    assert torch_equal(NX, Ne)
+    del Ne
+    rows = np.array([0, 1, 12345, 32767, 32768, n - 1])
+    Dr = D[torch_index(rows)].cpu().numpy()
+    np.testing.assert_array_equal(Dr, oracle.sssp_i32(W, rows))
+    Dh, NXh = D.cpu().numpy(), NX.cpu().numpy()
+    del D, NX
+    assert_walks(W, Dh, NXh, rows=rows)
 
 
 def torch_equal(a, b):
