@@ -153,8 +153,13 @@ __global__ __launch_bounds__(kBwdThreads) void backward_kernel(
 // Graphs of at most kBwdWaveMaxN vertices: one wave per destination, four
 // destinations per workgroup, wave-level ordering instead of workgroup
 // barriers (a destination's tree has few levels and few vertices per lane,
-// so barriers and idle lanes dominated the workgroup form).
+// so barriers and idle lanes dominated the workgroup form).  Per vertex and
+// destination the wave keeps 12 bytes of LDS -- child count and subtree sum
+// (32-bit, updated with LDS atomics), parent and queue slot (16-bit, n <=
+// 1024) -- so that three workgroups share a CU; the column is read eight
+// rows per lane at a time, all loads in flight before the first LDS store.
 constexpr int kBwdWaveMaxN = 1024;
+constexpr int kBwdWaveBytes = 12;           // LDS bytes per vertex and destination
 
 __device__ __forceinline__ void wave_sync_bwd() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -187,22 +192,37 @@ __global__ __launch_bounds__(256) void backward_wave_kernel(
     const int grp = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     const int j = grp * 4 + w;
     if (j >= n) return;                     // the whole wave; no workgroup barrier follows
-    int *par = bwd_lds + (int64_t)w * 4 * n_cap;
-    int *cnt = par + n_cap;
+    // this wave's arrays: cnt and S (n_cap 32-bit words each), then par and
+    // q (n_cap 16-bit entries each)
+    int *cnt = bwd_lds + (int64_t)w * (kBwdWaveBytes / 4) * n_cap;
     float *S = reinterpret_cast<float *>(cnt + n_cap);
-    int *q = reinterpret_cast<int *>(S + n_cap);
+    int16_t *par = reinterpret_cast<int16_t *>(S + n_cap);
+    int16_t *q = par + n_cap;
     int &tail = s_tail[w];
     const float *Gg = G + base;
     const int32_t *Ng = NX + base;
     float *dWg = dW + base;
     if (lane == 0) tail = 0;
-    for (int u = lane; u < n; u += 64) {
-        const int64_t o = (int64_t)u * ld + j;
-        const int v = Ng[o];
-        const bool on = u != j && v >= 0 && v < n;
-        par[u] = on ? v : -1;
-        S[u] = on ? Gg[o] : 0.0f;
-        cnt[u] = 0;
+    for (int u0 = 0; u0 < n; u0 += 8 * 64) {
+        int v[8];
+        float g[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int u = u0 + 64 * m + lane;
+            const int64_t o = (int64_t)(u < n ? u : 0) * ld + j;
+            v[m] = Ng[o];
+            g[m] = Gg[o];
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int u = u0 + 64 * m + lane;
+            if (u < n) {
+                const bool on = u != j && v[m] >= 0 && v[m] < n;
+                par[u] = (int16_t)(on ? v[m] : -1);
+                S[u] = on ? g[m] : 0.0f;
+                cnt[u] = 0;
+            }
+        }
     }
     wave_sync_bwd();
     for (int u = lane; u < n; u += 64) {
@@ -211,7 +231,7 @@ __global__ __launch_bounds__(256) void backward_wave_kernel(
     }
     wave_sync_bwd();
     for (int u = lane; u < n; u += 64)
-        if (par[u] >= 0 && cnt[u] == 0) q[atomicAdd(&tail, 1)] = u;
+        if (par[u] >= 0 && cnt[u] == 0) q[atomicAdd(&tail, 1)] = (int16_t)u;
     int head = 0;
     for (;;) {
         wave_sync_bwd();
@@ -224,7 +244,7 @@ __global__ __launch_bounds__(256) void backward_wave_kernel(
             cnt[u] = -1;                                      // processed
             if (v != j) {
                 atomicAdd(&S[v], sv);
-                if (atomicSub(&cnt[v], 1) == 1) q[atomicAdd(&tail, 1)] = v;
+                if (atomicSub(&cnt[v], 1) == 1) q[atomicAdd(&tail, 1)] = (int16_t)v;
             }
         }
         head = end;
@@ -307,7 +327,7 @@ hipError_t launch_backward(const BackwardPlan &b) {
     if (b.n_cap <= kBwdWaveMaxN) {
         const int groups = (b.n_cap + 3) / 4;
         const unsigned gx = (unsigned)(8 * ((groups + 7) / 8));
-        const size_t lds = (size_t)4 * 16 * b.n_cap;
+        const size_t lds = (size_t)4 * kBwdWaveBytes * b.n_cap;
         hipLaunchKernelGGL(backward_wave_kernel, dim3(gx, graphs), dim3(256), lds, b.stream, b.G, b.NX, b.dW, b.n,
                            b.ld, b.off, b.nv, b.n_cap, b.err);
     } else if (b.n_cap <= kBackwardLdsMaxN) {
