@@ -337,10 +337,12 @@ PHASE_NOTE = ("per kind of launch, the summed durations of its launches (HIP eve
               "and their sum exceeds ms_per_step")
 
 
-def auto_block(n: int) -> int:
+def auto_block(n: int, dtype: str = "i32") -> int:
     """The library's automatic block size for a single solve without a tuned
     entry."""
-    return 32 if n <= 32 else 64 if n <= 64 else 128
+    if n <= 32:
+        return 32
+    return 64 if n <= (3072 if dtype == "f64" else 4096) else 128
 
 
 def measure_single(torch, fw, Wd, nx, dtype, steps, warmup, block=0, schedule=0, eff_block=None,
@@ -350,7 +352,7 @@ def measure_single(torch, fw, Wd, nx, dtype, steps, warmup, block=0, schedule=0,
     roofline of the dominant kernel (phase 3, or the persistent kernel) and
     the summed kernel time per kind of launch."""
     n = Wd.shape[0]
-    bs = eff_block or block or auto_block(n)
+    bs = eff_block or block or auto_block(n, dtype)
     stream = torch.cuda.current_stream()
     D = torch.empty_like(Wd)
 
@@ -494,7 +496,7 @@ def main():
     Wd = torch.from_numpy(W).to(dev)
     del W
     NX = None if args.no_next else torch.empty((n, n), dtype=torch.int32, device=dev)
-    bs = args.block or auto_block(n)
+    bs = args.block or auto_block(n, args.dtype)
 
     def key(nx):
         return f"{args.dtype}_n{n}_bs{bs}_{'next' if nx is not None else 'dist'}"

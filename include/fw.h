@@ -30,7 +30,12 @@
  *    path matrix P stores the last intermediate vertex instead; a successor
  *    matrix walks a path in order.)  Where several shortest paths tie, any
  *    valid successor matrix may be returned; for a given input, block size
- *    and data type every schedule returns the same bits.
+ *    and data type every schedule returns the same bits.  Every successor
+ *    walk reaches its destination when the graph has no cycle of zero total
+ *    weight; with zero-weight cycles the distances stay exact, but a walk may
+ *    circle inside such a cycle (the blocked rounds relax against bands that
+ *    already hold the whole round's intermediate vertices, so a path through
+ *    a zero-weight cycle can tie with its shortcut).
  *  - Argument errors are detected on the host and returned before anything
  *    is enqueued; the text is then available from fw_last_error().  Errors
  *    found by the device (validate mode, dependency-wait timeout) are

@@ -166,9 +166,20 @@ int tuned_solve(fw::DType dt, bool next, int64_t n) {
     return it == g_tuned_solve.end() ? 0 : it->second;
 }
 
-int auto_block(int64_t n) {
+// Automatic block size (no tuned entry).  Up to a few thousand vertices the
+// rounds are latency-bound -- each one's phase 1 is a chain of BS dependent
+// steps and its band tiles are few -- and block 64 halves that chain for
+// twice the rounds; beyond, block 128's longer tiles (and the direct-copy
+// phase 3) win.  Measured on MI355X, three launches, ms per solve at block 64
+// against 128: int32 with successors n = 512: 1.06 / 1.55, 2048: 3.94 /
+// 5.39, 4096: 10.3 / 10.9, 5120: 16.4 / 14.9; float32 with successors 4096:
+// 13.2 / 13.8, 6144: 29.9 / 25.6; int32 distances only 2048: 2.94 / 3.45,
+// 3072: 5.60 / 5.49; float32 distances only 4096: 7.75 / 8.88; float64 with
+// successors 2048: 6.41 / 9.10, 4096: 23.6 / 22.5.
+int auto_block(fw::DType dt, int64_t n) {
     if (n <= 32) return 32;
     if (n <= 64) return 64;
+    if (n <= (dt == fw::DType::F64 ? 3072 : 4096)) return 64;
     return 128;
 }
 
@@ -201,7 +212,7 @@ fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
     p.next = next;
     p.n = n;
     p.ld = ld;
-    p.bs = persistent ? fw::kTile : (o.block ? o.block : auto_block(n));
+    p.bs = persistent ? fw::kTile : (o.block ? o.block : auto_block(dt, n));
     p.rounds = (int)((n + p.bs - 1) / p.bs);
     p.nt = (int)((n + fw::kTile - 1) / fw::kTile);
     p.vec = (ld % 4 == 0) && ((uintptr_t)dist % (4 * fw::dtype_bytes(dt)) == 0);   // 4-element vector accesses

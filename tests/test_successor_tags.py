@@ -130,3 +130,93 @@ def test_tags_are_not_successors_themselves():
     assert t.sum() > 20
     raw = np.where(t, Nt & (TAG - 1), Nt)
     assert not np.array_equal(raw, Ne)
+
+
+def _blocked_product(W, bs):
+    """Blocked FW in the product form of the GPU kernels (phase 2 against the
+    closed diagonal block and the band as it stood, phase 3 against both
+    bands after phase 2; in each, the first k reaching the strict minimum),
+    eager successors."""
+    n = W.shape[0]
+    D = np.minimum(W.astype(np.int64), INF)
+    np.fill_diagonal(D, 0)
+    NX = np.where(D < INF, np.arange(n)[None, :], -1).astype(np.int64)
+
+    def product(rows, cols, ks, Acol, Brow, NXA):
+        # C <- min(C, A (x) B), first k of the strict minimum; A/B/NXA frozen
+        for i in rows:
+            for j in cols:
+                best, arg = D[i, j], -1
+                for k in ks:
+                    a, b = Acol[i][k], Brow[k][j]
+                    if a < INF and b < INF and a + b < best:
+                        best, arg = a + b, k
+                if arg >= 0:
+                    D[i, j] = best
+                    NX[i, j] = NXA[i][arg]
+
+    for K in range((n + bs - 1) // bs):
+        blk = list(range(K * bs, min(n, K * bs + bs)))
+        rest = [v for v in range(n) if v < blk[0] or v > blk[-1]]
+        for k in blk:                                      # phase 1, in place
+            for i in blk:
+                for j in blk:
+                    if D[i, k] < INF and D[k, j] < INF and D[i, k] + D[k, j] < D[i, j]:
+                        D[i, j] = D[i, k] + D[k, j]
+                        NX[i, j] = NX[i, k]
+        Dc, Nc = D.copy(), NX.copy()
+        product(blk, rest, blk, Dc, Dc, Nc)                # row band: A = closed block, B = old band
+        product(rest, blk, blk, Dc, Dc, Nc)                # column band: A = old band, B = closed block
+        Dc, Nc = D.copy(), NX.copy()
+        product(rest, rest, blk, Dc, Dc, Nc)               # phase 3: both bands after phase 2
+    return D, NX
+
+
+def _walks_end(NX, n):
+    for i in range(n):
+        for j in range(n):
+            if NX[i, j] < 0:
+                continue
+            v, steps = i, 0
+            while v != j:
+                v = NX[v, j]
+                steps += 1
+                if steps > n:
+                    return False
+    return True
+
+
+def test_product_form_walks_end_without_zero_cycles():
+    """Positive cycles only (zero-weight edges allowed on a DAG): the
+    product form's successor walks all reach their destination."""
+    rng = np.random.default_rng(5)
+    n = 40
+    W = _graph(rng, n, 0.15, 2)
+    lower = np.tril(np.ones((n, n), bool), -1)
+    W[lower & (W == 0)] = 1                            # zero weights only on edges i -> j, i < j
+    D, NX = _blocked_product(W, 8)
+    Do, _ = oracle.fw_i32(W.astype(np.int32))
+    np.testing.assert_array_equal(D, Do)
+    assert _walks_end(NX, n)
+
+
+def test_product_form_can_loop_on_zero_cycles():
+    """With zero-weight cycles the distances stay exact, but a successor walk
+    can circle inside a zero-weight cycle: phase 3 takes both bands after
+    phase 2, so a path i -> k and a path k -> j may share a vertex x, and
+    the zero-weight cycle through x and k then ties with the shortcut
+    through x.  The plain triple loop never does this (its operands at step k
+    use intermediates below k only)."""
+    rng = np.random.default_rng(7)
+    found = False
+    for _ in range(20):
+        n = 36
+        W = _graph(rng, n, 0.08, 1)                    # sparse, weights 0 or 1: zero cycles
+        D, NX = _blocked_product(W, 6)
+        Do, NXo = oracle.fw_i32(W.astype(np.int32))
+        np.testing.assert_array_equal(D, Do)
+        assert _walks_end(NXo, n)
+        if not _walks_end(NX, n):
+            found = True
+            break
+    assert found
