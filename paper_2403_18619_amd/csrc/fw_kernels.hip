@@ -21,7 +21,9 @@
 // Successor matrix: when C[i][j] strictly improves, NX[i][j] takes the
 // successor of the A operand's entry, NX[i][K*BS + k*], where k* is the first
 // k (in increasing order) that reaches the new minimum.  With a strict
-// comparison that choice is the same in every schedule and tile order.
+// comparison that choice is the same in every schedule and tile order.  (The
+// int32 direct-copy phase 3 records K*BS + k* as a tag instead and looks the
+// successor up once the last round is done: resolve_next_kernel.)
 //
 // Arithmetic: int32 distances run as uint32 (INF = 2^30, INF + INF = 2^31
 // does not wrap); float32 and float64 as IEEE single / double.  Every
