@@ -1014,8 +1014,8 @@ __device__ __forceinline__ void minplus_tile(U *__restrict__ D, int32_t *__restr
 // Tile of a phase-3 launch: part 1 = the next band's tiles (row and column
 // K + 1; block size = tile edge), part 2 = the rest, part 0 = all; -1 = none.
 // Workgroups are dealt to the eight XCDs round-robin; each XCD gets a
-// contiguous run of tiles, so that tiles sharing a row of A meet in the same
-// L2.
+// contiguous run of positions in the tile order below.
+constexpr int kBandRows = 8;
 __device__ __forceinline__ int64_t phase3_tile(int part, int K, int nt) {
     if (part == 1) {
         const int q = (int)blockIdx.x, nx1 = K + 1;
@@ -1025,8 +1025,16 @@ __device__ __forceinline__ int64_t phase3_tile(int part, int K, int nt) {
     }
     const int64_t tiles = (int64_t)nt * nt;
     const int64_t per = (tiles + 7) / 8;
-    const int64_t idx = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (idx >= tiles) return -1;
+    const int64_t g = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (g >= tiles) return -1;
+    // position g -> tile: bands of kBandRows tile rows, column by column
+    // inside a band, so that the tiles one XCD runs at once form a compact
+    // block whose operand panel rows (A' of its rows, B' of its columns)
+    // stay in that XCD's L2
+    const int64_t band = g / ((int64_t)kBandRows * nt);
+    const int64_t brows = imin64(kBandRows, nt - band * kBandRows);
+    const int64_t o = g - band * kBandRows * nt;
+    const int64_t idx = (band * kBandRows + o % brows) * nt + o / brows;
     if (part == 2 && (idx / nt == K + 1 || idx % nt == K + 1)) return -1;   // done by part 1
     return idx;
 }
