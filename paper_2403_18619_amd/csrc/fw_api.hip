@@ -233,7 +233,7 @@ fw_status solve(fw::DType dt, void *dist, int32_t *next, int64_t n, int64_t ld,
     const bool packed = !persistent && dt == fw::DType::I32 && next && !p.eager_argmin;
     if (packed) {
         // band maxima for the packed-key phase 3 (two round parities)
-        s = grow_ints(&p.work->bmax, &p.work->bmax_ints, 4 * (int64_t)p.nt, "band maxima");
+        s = grow_ints(&p.work->bmax, &p.work->bmax_ints, 4 * (int64_t)p.nt + 2, "band maxima");
         if (s != FW_OK) return s;
     }
     // the direct-copy phase 3 (block 128, aligned rows): int32 with successors

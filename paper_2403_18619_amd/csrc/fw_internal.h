@@ -21,7 +21,7 @@ struct DeviceWork {
     int64_t batch_ints = 0;    // its capacity
     int *bwd = nullptr;        // backward, large n: per-workgroup vertex arrays
     int64_t bwd_ints = 0;      // its capacity
-    int *bmax = nullptr;       // three-launch schedule: band maxima, 4 nt ints
+    int *bmax = nullptr;       // three-launch schedule: band maxima, 4 nt ints, then 2 block maxima
     int64_t bmax_ints = 0;     // its capacity
     int *panel = nullptr;      // three-launch, block 128: packed operand panels, 4 x 128 x 128 nt
     int64_t panel_ints = 0;    // its capacity

@@ -139,9 +139,13 @@ template <typename U, int BS, bool NXLDS> struct alignas(4 * sizeof(U)) Phase1Sm
     int32_t nx[NXLDS ? BS : 1][BS + 1];          // odd pitch: column reads hit distinct banks
 };
 
+// s_max (32-bit entries; may be null): an LDS word that receives, by atomic
+// maximum, the largest finite entry of the closed block (the caller zeroes
+// it before and reads it after a barrier).
 template <typename U, bool NEXT, int BS, int NT, bool NXLDS>
 __device__ __forceinline__ void phase1_block(U *__restrict__ D, int32_t *__restrict__ NX, int64_t n,
-                                             int64_t ld, int K, Phase1Smem<U, BS, NXLDS> &sm) {
+                                             int64_t ld, int K, Phase1Smem<U, BS, NXLDS> &sm,
+                                             uint32_t *s_max = nullptr) {
     constexpr int TX = NT / 16;
     constexpr int MR = BS / 16, MC = BS / TX;
     constexpr bool NXR = NEXT && !NXLDS;         // successors in registers
@@ -242,6 +246,7 @@ __device__ __forceinline__ void phase1_block(U *__restrict__ D, int32_t *__restr
         }
     }
 
+    uint32_t m = 0;
 #pragma unroll
     for (int r = 0; r < MR; ++r) {
 #pragma unroll
@@ -250,8 +255,15 @@ __device__ __forceinline__ void phase1_block(U *__restrict__ D, int32_t *__restr
             if (li < bk && lj < bk) {
                 D[(b0 + li) * ld + b0 + lj] = d[r][c];
                 if (NXR) NX[(b0 + li) * ld + b0 + lj] = nx[NXR ? r : 0][NXR ? c : 0];
+                if constexpr (sizeof(U) == 4 && !std::is_same<U, float>::value) {
+                    const uint32_t v = (uint32_t)d[r][c];
+                    if (v < kInfU && v > m) m = v;
+                }
             }
         }
+    }
+    if constexpr (sizeof(U) == 4 && !std::is_same<U, float>::value) {
+        if (s_max) atomicMax(s_max, m);
     }
     if (NXL) {
         for (int q = t; q < bk * bk; q += NT) {
@@ -261,11 +273,20 @@ __device__ __forceinline__ void phase1_block(U *__restrict__ D, int32_t *__restr
     }
 }
 
+// dmax (int32 with successors in the three-launch schedule, else null): the
+// closed block's largest finite entry goes to dmax[K & 1], for the band tiles'
+// packed-key test.
 template <typename U, bool NEXT, int BS>
 __global__ __launch_bounds__(256) void phase1_kernel(U *__restrict__ D, int32_t *__restrict__ NX,
-                                                     int64_t n, int64_t ld, int K) {
+                                                     int64_t n, int64_t ld, int K, int *__restrict__ dmax) {
     __shared__ Phase1Smem<U, BS, false> sm;
-    phase1_block<U, NEXT, BS, 256, false>(D, NX, n, ld, K, sm);
+    __shared__ uint32_t s_max;
+    if (threadIdx.x == 0) s_max = 0;               // ordered by phase1_block's first barrier
+    phase1_block<U, NEXT, BS, 256, false>(D, NX, n, ld, K, sm, dmax ? &s_max : nullptr);
+    if (dmax) {
+        __syncthreads();
+        if (threadIdx.x == 0) dmax[K & 1] = (int)s_max;
+    }
 }
 
 // Closure of an n x n block (n <= S) by one workgroup of NT threads: phase 1
@@ -558,7 +579,7 @@ __device__ __forceinline__ void minplus_tile_impl(U *__restrict__ D, int32_t *__
     constexpr bool PACKABLE = ARGMIN == 2 && std::is_same<U, uint32_t>::value;
     constexpr bool fast = PACKABLE && PACKED;       // packed keys for this tile
     int *const bm = PACKABLE && bmax ? bmax + (K & 1) * 2 * nt : nullptr;
-    if constexpr (PACKABLE && !PACKED) {
+    if constexpr (PACKABLE) {
         if (t == 0) sm.bmax_s = 0;
     }
 
@@ -866,9 +887,12 @@ __device__ __forceinline__ void minplus_tile_impl(U *__restrict__ D, int32_t *__
         __syncthreads();
     }
 
-    // ---- a band tile publishes its largest finite entry (packed keys)
-    if constexpr (PACKABLE && !PACKED) {
+    // ---- a band tile publishes its largest finite entry (packed keys).  In
+    // the packed form an entry that stayed infinite holds the clamped value
+    // S (every finite result there is a sum below S), so S counts as infinite.
+    if constexpr (PACKABLE) {
         if (mode != 0 && bm) {
+            constexpr uint32_t fin = PACKED ? kPackSat : kInfU;
             uint32_t m = 0;
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
@@ -876,7 +900,7 @@ __device__ __forceinline__ void minplus_tile_impl(U *__restrict__ D, int32_t *__
 #pragma unroll
                 for (int c = 0; c < CPT; ++c) {
                     const uint32_t v = (uint32_t)acc[r][c];
-                    if (rv && G::col_off(txe, c) < cols_valid && v < kInfU) m = v > m ? v : m;
+                    if (rv && G::col_off(txe, c) < cols_valid && v < fin) m = v > m ? v : m;
                 }
             }
             atomicMax(&sm.bmax_s, m);
@@ -991,7 +1015,9 @@ __device__ __forceinline__ void minplus_tile_impl(U *__restrict__ D, int32_t *__
 
 // One 128 x 128 tile: packed keys when the round's operand panels allow them
 // (int32 with successors, phase 3), the general form otherwise.
-template <typename U, int ARGMIN, bool VEC>
+// BANDS: band tiles may take packed keys too (the three-launch phase 2,
+// where phase 1 publishes the diagonal block's maximum).
+template <typename U, int ARGMIN, bool VEC, bool BANDS = false>
 __device__ __forceinline__ void minplus_tile(U *__restrict__ D, int32_t *__restrict__ NX, int64_t n, int64_t ld,
                                              int K, int BS, int mode, int64_t row0, int64_t col0,
                                              MinplusSmem<U, ARGMIN> &sm, int *__restrict__ bmax, int nt,
@@ -1004,6 +1030,38 @@ __device__ __forceinline__ void minplus_tile(U *__restrict__ D, int32_t *__restr
             if (ma < kPackLimit && mb < kPackLimit) {
                 minplus_tile_impl<U, ARGMIN, VEC, true>(D, NX, n, ld, K, BS, mode, row0, col0, sm, bmax, nt,
                                                         nullptr, 0);
+                return;
+            }
+        } else if (BANDS && mode != 0 && bmax) {
+            // a band tile: its operands are the closed diagonal block (largest
+            // finite entry published by phase 1) and the tile itself
+            const uint32_t md = (uint32_t)bmax[4 * nt + (K & 1)];
+            bool big = md >= kPackLimit;               // uniform
+            if (!big) {
+                using G = Geo<MinplusSmem<U, ARGMIN>::NT>;
+                const int64_t b0 = (int64_t)K * BS;
+                const int bk = (int)imin64((int64_t)BS, n - b0);
+                const int rows_valid = (mode == 1) ? bk : (int)imin64(kTile, n - row0);
+                const int cols_valid = (mode == 2) ? bk : (int)imin64(kTile, n - col0);
+                const int tx = (int)threadIdx.x % G::txn, ty = (int)threadIdx.x / G::txn;
+                bool mine = false;
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int li = G::row_off(ty, r);
+                    if (li >= rows_valid) continue;
+#pragma unroll
+                    for (int c = 0; c < G::cpt; ++c) {
+                        const int lj = G::col_off(tx, c);
+                        if (lj >= cols_valid) continue;
+                        const uint32_t v = D[(row0 + li) * ld + col0 + lj];
+                        mine = mine || (v >= kPackLimit && v < kInfU);
+                    }
+                }
+                big = __syncthreads_or((int)mine) != 0;
+            }
+            if (!big) {
+                minplus_tile_impl<U, ARGMIN, VEC, true>(D, NX, n, ld, K, BS, mode, row0, col0, sm, bmax, nt,
+                                                        panel, ppitch);
                 return;
             }
         }
@@ -1062,7 +1120,7 @@ __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (Occ<U, ARGMIN>::waves_s
     }
     int64_t row0, col0;
     if (!band_tile(mode, idx, n, b0, b1, nt, row0, col0)) return;
-    minplus_tile<U, ARGMIN, VEC>(D, NX, n, ld, K, BS, mode, row0, col0, sm, bmax, nt, panel, ppitch);
+    minplus_tile<U, ARGMIN, VEC, PHASE == 2>(D, NX, n, ld, K, BS, mode, row0, col0, sm, bmax, nt, panel, ppitch);
 }
 
 // ------------------------------------------- phase 3: direct-copy kernel
@@ -2172,10 +2230,13 @@ hipError_t init_t(const Plan &p) {
 
 template <typename U, bool NEXT>
 hipError_t phase1_t(const Plan &p, int K) {
+    // the block maximum for packed band tiles: int32 with deferred successors
+    int *dmax = (std::is_same<U, uint32_t>::value && NEXT && !p.eager_argmin && p.work->bmax)
+                        ? p.work->bmax + 4 * (int64_t)p.nt : nullptr;
     switch (p.bs) {
-    case 32: hipLaunchKernelGGL((phase1_kernel<U, NEXT, 32>), dim3(1), dim3(256), 0, p.stream, (U *)p.dist, p.next, p.n, p.ld, K); break;
-    case 64: hipLaunchKernelGGL((phase1_kernel<U, NEXT, 64>), dim3(1), dim3(256), 0, p.stream, (U *)p.dist, p.next, p.n, p.ld, K); break;
-    case 128: hipLaunchKernelGGL((phase1_kernel<U, NEXT, 128>), dim3(1), dim3(256), 0, p.stream, (U *)p.dist, p.next, p.n, p.ld, K); break;
+    case 32: hipLaunchKernelGGL((phase1_kernel<U, NEXT, 32>), dim3(1), dim3(256), 0, p.stream, (U *)p.dist, p.next, p.n, p.ld, K, dmax); break;
+    case 64: hipLaunchKernelGGL((phase1_kernel<U, NEXT, 64>), dim3(1), dim3(256), 0, p.stream, (U *)p.dist, p.next, p.n, p.ld, K, dmax); break;
+    case 128: hipLaunchKernelGGL((phase1_kernel<U, NEXT, 128>), dim3(1), dim3(256), 0, p.stream, (U *)p.dist, p.next, p.n, p.ld, K, dmax); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
