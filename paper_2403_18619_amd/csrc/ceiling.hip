@@ -8,6 +8,13 @@
 //                 v_min3_u32 per pair of k's and entry, operands in registers
 //                 (8 x 4 entries per thread); "compiler" = the compiler's own
 //                 order, "pinned" = add, add, min3 entry by entry
+//   eager f32   : the eager float32 relaxation with a successor (the batched
+//                 solve's closures and tiles), one k per step, operands in
+//                 registers (8 x 4 entries per thread): v_add_f32,
+//                 v_cmp_lt_f32, a minimum on the bit patterns and the
+//                 successor select -- four VALU instructions per relaxation
+//   min f32     : the float32 distances-only relaxation of the same tile, two
+//                 k's per step (two v_add_f32 and one three-way minimum)
 //   lds <form>  : ds_read_b128 of the tile's operand patterns, as in the
 //                 tile's k loop: "A" (32 lanes share an address), "B" (two
 //                 lanes share an address) and "distinct"
@@ -80,6 +87,57 @@ __global__ __launch_bounds__(kThreads) void mix_kernel(uint32_t *out, int iters,
     uint32_t x = 0;
     for (int r = 0; r < 8; ++r)
         for (int c = 0; c < 4; ++c) x ^= acc[r][c];
+    if (threadIdx.x == 0) pad[0] = x;
+    out[blockIdx.x * kThreads + threadIdx.x] = x;
+}
+
+// The float32 relaxations of the batched solve, operands in registers.
+// EAGER: d <- min(d, a + b) and the successor select, one k per step; else
+// distances only, two k's per step.  Values are non-negative, so the minimum
+// is taken on bit patterns, as the solve does.
+template <bool EAGER>
+__global__ __launch_bounds__(kThreads) void f32_kernel(uint32_t *out, int iters, uint32_t seed) {
+    extern __shared__ uint32_t pad[];
+    const uint32_t t = threadIdx.x + blockIdx.x * kThreads + seed;
+    float acc[8][4], a[8], b[4], a2[8], b2[4];
+    int32_t idx[8][4], na[8];
+    for (int r = 0; r < 8; ++r) {
+        a[r] = (float)((t + r) % 97) * 0.25f;
+        a2[r] = (float)((t + 3 * r) % 89) * 0.25f;
+        na[r] = (int32_t)(t + r);
+    }
+    for (int c = 0; c < 4; ++c) {
+        b[c] = (float)((t >> 3) % 61 + c) * 0.125f;
+        b2[c] = (float)((t >> 5) % 53 + c) * 0.125f;
+    }
+    for (int r = 0; r < 8; ++r)
+        for (int c = 0; c < 4; ++c) {
+            acc[r][c] = 1e30f;
+            idx[r][c] = -1;
+        }
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) asm volatile("" : "+v"(a[r]), "+v"(a2[r]), "+v"(na[r]));
+#pragma unroll
+        for (int c = 0; c < 4; ++c) asm volatile("" : "+v"(b[c]), "+v"(b2[c]));
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if constexpr (EAGER) {
+                    const float x = a[r] + b[c];
+                    const bool lt = x < acc[r][c];
+                    acc[r][c] = __uint_as_float(min(__float_as_uint(acc[r][c]), __float_as_uint(x)));
+                    idx[r][c] = lt ? na[r] : idx[r][c];
+                } else {
+                    const uint32_t x = __float_as_uint(a[r] + b[c]), y = __float_as_uint(a2[r] + b2[c]);
+                    acc[r][c] = __uint_as_float(min(min(__float_as_uint(acc[r][c]), x), y));
+                }
+            }
+    }
+    uint32_t x = 0;
+    for (int r = 0; r < 8; ++r)
+        for (int c = 0; c < 4; ++c) x ^= __float_as_uint(acc[r][c]) ^ (uint32_t)idx[r][c];
     if (threadIdx.x == 0) pad[0] = x;
     out[blockIdx.x * kThreads + threadIdx.x] = x;
 }
@@ -175,6 +233,17 @@ int main() {
         const double relax = (double)grid * kThreads * iters * 64.0;
         std::printf("mix  %-10s %8.3f ms  %.4e relaxations/s (2 x v_add_u32 + v_min3_u32 per pair of k's)\n",
                     pinned ? "pinned" : "compiler", ms, relax / (ms * 1e-3));
+    }
+    // float32 relaxations; the fraction is of the 2-operation-per-relaxation
+    // rate (128 lanes per clock per CU)
+    const double peak_relax = cus * ghz * 1e9 * 128.0 / 2.0;
+    for (int eager = 1; eager >= 0 && !rc; --eager) {
+        const int iters = 20000;
+        if (!launch_timed(eager ? f32_kernel<true> : f32_kernel<false>, grid, lds, out, iters, &ms)) { rc = 1; break; }
+        const double relax = (double)grid * kThreads * iters * (eager ? 32.0 : 64.0);
+        const double rate = relax / (ms * 1e-3);
+        std::printf("%-15s %8.3f ms  %.4e relaxations/s (%.3f of 2 operations per relaxation at 128 lanes/clock)\n",
+                    eager ? "eager f32" : "min f32", ms, rate, rate / peak_relax);
     }
     const char *lds_names[3] = {"A", "B", "distinct"};
     void (*ldsk[3])(uint32_t *, int, uint32_t) = {lds_kernel<0>, lds_kernel<1>, lds_kernel<2>};

@@ -65,6 +65,18 @@ template <> struct Arith<double> {
     static __device__ __forceinline__ double mn(double a, double b) { return __builtin_fmin(a, b); }
 };
 
+// One eager relaxation's new value, min(d, s), when the caller also needs
+// whether s < d (to move the successor).  Taking the minimum apart from the
+// comparison leaves the successor select as the only instruction that waits
+// on the comparison's lane mask.  Same bits as s < d ? s : d: distances and
+// sums are never NaN or -0, and non-negative floats (+inf included) order as
+// their bit patterns do.
+__device__ __forceinline__ uint32_t eager_min(uint32_t d, uint32_t s) { return min(d, s); }
+__device__ __forceinline__ float eager_min(float d, float s) {
+    return __uint_as_float(min(__float_as_uint(d), __float_as_uint(s)));
+}
+__device__ __forceinline__ double eager_min(double d, double s) { return s < d ? s : d; }
+
 // Launch bounds.  Threads per workgroup of the min-plus code: 512 for the
 // successor variants (8 x 4 entries per thread: a value and a chunk minimum,
 // or a value and an index, per entry), 256 for distances only (8 x 8).
@@ -100,6 +112,48 @@ __device__ __forceinline__ double norm_weight(double v, bool diag, bool &bad) {
     if (diag) return 0.0;
     if (v != v) return __builtin_inf();
     return v == 0.0 ? 0.0 : v;
+}
+
+// Normalise entries start, start + stride, ... of one graph's n x n
+// row-major block (as init_kernel).  Eight loads are in flight per thread
+// before any entry is rewritten, and the row and column of the next entry
+// are stepped, not divided out, so that the loop costs one memory round trip
+// per eight entries.  Returns whether a negative or NaN weight was seen.
+template <typename U, bool NEXT>
+__device__ __forceinline__ bool normalise_graph(U *__restrict__ Dg, int32_t *__restrict__ NXg, int64_t n,
+                                                int64_t start, int64_t stride) {
+    constexpr int UNR = 8;
+    const int64_t nn = n * n;
+    if (start >= nn) return false;
+    const int64_t di = stride / n, dj = stride % n;
+    int64_t i = start / n, j = start % n;
+    bool any_bad = false;
+    for (int64_t base = start; base < nn; base += UNR * stride) {
+        U w[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int64_t q = base + u * stride;
+            w[u] = q < nn ? Dg[q] : U(0);
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int64_t q = base + u * stride;
+            if (q < nn) {
+                bool bad;
+                const U v = norm_weight(w[u], i == j, bad);
+                any_bad |= bad;
+                Dg[q] = v;
+                if (NEXT) NXg[q] = (i == j) ? (int32_t)i : (v < Arith<U>::inf() ? (int32_t)j : -1);
+            }
+            i += di;
+            j += dj;
+            if (j >= n) {                          // dj < n and j < n: one wrap at most
+                j -= n;
+                ++i;
+            }
+        }
+    }
+    return any_bad;
 }
 
 template <typename U>
@@ -216,7 +270,7 @@ __device__ __forceinline__ void phase1_block(U *__restrict__ D, int32_t *__restr
                     for (int c = 0; c < MC; ++c) {
                         const U s = a[r] + b[c];
                         const bool lt = s < d[r][c];
-                        d[r][c] = lt ? s : d[r][c];
+                        d[r][c] = eager_min(d[r][c], s);
                         if (NXR) nx[NXR ? r : 0][NXR ? c : 0] = lt ? na[r] : nx[NXR ? r : 0][NXR ? c : 0];
                         if (NXL && lt) sm.nx[NXL ? tyo * MR + r : 0][txo * MC + c] = na[r];
                     }
@@ -350,7 +404,7 @@ __device__ __forceinline__ void closure_block(U *__restrict__ D, int32_t *__rest
             for (int c = 0; c < MC; ++c) {
                 const U sum = a[r] + b[c];
                 const bool lt = sum < d[r][c];
-                d[r][c] = lt ? sum : d[r][c];
+                d[r][c] = eager_min(d[r][c], sum);
                 if (NEXT) nx[NEXT ? r : 0][NEXT ? c : 0] = lt ? na[r] : nx[NEXT ? r : 0][NEXT ? c : 0];
             }
         }
@@ -568,13 +622,33 @@ __device__ __forceinline__ void minplus_tile_impl(U *__restrict__ D, int32_t *__
     // an opaque thread index (see phase1_block)
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));
-    const int tx = t % G::txn, ty = t / G::txn;
+    // Thread -> patch.  The eager variant gives each wave 16 x 4 threads: one
+    // 64-column half of the tile and 16 rows of each row half, so that a wave
+    // whose columns, or rows, all lie past a ragged tile's edge has nothing
+    // to relax; the other variants keep 32 x 2 threads per wave.
+    int tx, ty;
+    if constexpr (ARGMIN == 1 && NT == 512) {
+        const int w = t >> 6, l = t & 63;
+        tx = (w & 1) * 16 + (l & 15);
+        ty = (w >> 1) * 4 + (l >> 4);
+    } else {
+        tx = t % G::txn;
+        ty = t / G::txn;
+    }
     const int64_t b0 = (int64_t)K * BS;
     const int bk = (int)imin64((int64_t)BS, n - b0);
     const int64_t b1 = b0 + bk;
     // number of valid rows / columns of C (and of A's rows, B's columns)
     const int rows_valid = (mode == 1) ? bk : (int)imin64(kTile, n - row0);
     const int cols_valid = (mode == 2) ? bk : (int)imin64(kTile, n - col0);
+    // eager variant: this wave's columns (64 w&1 .. +63) or rows (16 (w>>1)
+    // .. +15 in each half) all invalid -- it stages operands and joins the
+    // barriers, and skips the relaxations
+    bool idle_wave = false;
+    if constexpr (ARGMIN == 1 && NT == 512) {
+        const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+        idle_wave = (w & 1) * 64 >= cols_valid || (w >> 1) * 16 >= rows_valid;
+    }
     constexpr bool use_vec = VEC;
     constexpr bool PACKABLE = ARGMIN == 2 && std::is_same<U, uint32_t>::value;
     constexpr bool fast = PACKABLE && PACKED;       // packed keys for this tile
@@ -709,14 +783,16 @@ __device__ __forceinline__ void minplus_tile_impl(U *__restrict__ D, int32_t *__
                         for (int c = 0; c < CPT; ++c) {
                             const U s = a[r] + b[c];
                             const bool lt = s < acc[r][c];
-                            acc[r][c] = lt ? s : acc[r][c];
+                            acc[r][c] = eager_min(acc[r][c], s);
                             idx[r][c] = lt ? kg : idx[r][c];
                         }
                     }
                 }
             };
-            if (rows_valid > 64) eager(std::integral_constant<int, 8>{});
-            else eager(std::integral_constant<int, 4>{});
+            if (!idle_wave) {
+                if (rows_valid > 64) eager(std::integral_constant<int, 8>{});
+                else eager(std::integral_constant<int, 4>{});
+            }
         } else if constexpr (ARGMIN == 0) {
 #pragma unroll 1
             for (int kk = 0; kk < KC; kk += 2) {
@@ -2075,15 +2151,9 @@ __global__ __launch_bounds__(256) void batch_init_kernel(U *__restrict__ D, int3
     if (n <= 0 || n > n_max) return;
     U *Dg = D + off[g];
     int32_t *NXg = NX ? NX + off[g] : nullptr;
-    bool any_bad = false;
-    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n * n; q += (int64_t)gridDim.x * 256) {
-        const int64_t i = q / n, j = q % n;
-        bool bad;
-        const U w = norm_weight(Dg[q], i == j, bad);
-        any_bad |= bad;
-        Dg[q] = w;
-        if (NXg) NXg[q] = (i == j) ? (int32_t)i : (w < Arith<U>::inf() ? (int32_t)j : -1);
-    }
+    const int64_t start = (int64_t)blockIdx.x * 256 + threadIdx.x, stride = (int64_t)gridDim.x * 256;
+    const bool any_bad = NXg ? normalise_graph<U, true>(Dg, NXg, n, start, stride)
+                             : normalise_graph<U, false>(Dg, NXg, n, start, stride);
     if (validate && any_bad) atomicCAS(err, 0, 1);
 }
 
@@ -2153,15 +2223,7 @@ __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (sizeof(U) == 4 && ARGMI
     U *Dg = D + off[g];
     int32_t *NXg = NEXT ? NX + off[g] : nullptr;
     // normalise the input (as init_kernel), entries of this graph only
-    bool any_bad = false;
-    for (int64_t q = threadIdx.x; q < n * n; q += NT) {
-        const int64_t i = q / n, j = q % n;
-        bool bad;
-        const U w = norm_weight(Dg[q], i == j, bad);
-        any_bad |= bad;
-        Dg[q] = w;
-        if (NEXT) NXg[q] = (i == j) ? (int32_t)i : (w < Arith<U>::inf() ? (int32_t)j : -1);
-    }
+    const bool any_bad = normalise_graph<U, NEXT>(Dg, NXg, n, threadIdx.x, NT);
     if (validate && any_bad) atomicCAS(err, 0, 1);
     __syncthreads();
     // at most 64 vertices (32-bit entries): the one-round solve by
@@ -2179,7 +2241,18 @@ __global__ __launch_bounds__((Occ<U, ARGMIN>::threads), (sizeof(U) == 4 && ARGMI
     for (int K = 0; K < R; ++K) {
         const int64_t b0 = (int64_t)K * BS;
         const int64_t b1 = b0 + imin64((int64_t)BS, n - b0);
-        phase1_any<U, NEXT, NT>(Dg, NXg, n, n, K, sm);
+        // a last diagonal block of at most 64 vertices (32-bit entries) is
+        // closed by the 64 x 64 patch (same arithmetic, order and successor
+        // choice), not by the 128 x 128 one
+        bool short_block = false;
+        if constexpr (sizeof(U) == 4) {
+            if (b1 - b0 <= 64) {
+                closure_block<U, NEXT, 64, NT>(Dg + b0 * n + b0, NEXT ? NXg + b0 * n + b0 : nullptr, b1 - b0, n,
+                                               sm.small);
+                short_block = true;
+            }
+        }
+        if (!short_block) phase1_any<U, NEXT, NT>(Dg, NXg, n, n, K, sm);
         __syncthreads();
         if (R == 1) break;
         for (int q = 0; q < 2 * nt; ++q) {          // row band, then column band
