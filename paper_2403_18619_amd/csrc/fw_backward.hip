@@ -151,20 +151,29 @@ __global__ __launch_bounds__(kBwdThreads) void backward_kernel(
 }
 
 // Graphs of at most kBwdWaveMaxN vertices: one wave per destination, four
-// destinations per workgroup, wave-level ordering instead of workgroup
-// barriers (a destination's tree has few levels and few vertices per lane,
-// so barriers and idle lanes dominated the workgroup form).  Per vertex and
-// destination the wave keeps 12 bytes of LDS -- child count and subtree sum
-// (32-bit, updated with LDS atomics), parent and queue slot (16-bit, n <=
-// 1024) -- so that three workgroups share a CU; the column is read eight
-// rows per lane at a time, all loads in flight before the first LDS store.
+// neighbouring destinations j0 .. j0+3 per workgroup, wave-level ordering
+// instead of workgroup barriers while the trees are processed (a
+// destination's tree has few levels and few vertices per lane, so barriers
+// and idle lanes dominated the workgroup form).  Per vertex and destination
+// the wave keeps 12 bytes of LDS -- child count and subtree sum (32-bit,
+// updated with LDS atomics), parent and queue slot (16-bit, n <= 1024) -- so
+// that three workgroups share a CU.  The workgroup reads and writes its four
+// columns together: four lanes take the four entries of one row, so that one
+// access of a wave touches 16 rows (cache lines) rather than 64, and each
+// entry goes to, or comes from, its destination wave's arrays (eight rows per
+// lane in flight before the first LDS store).
 constexpr int kBwdWaveMaxN = 1024;
 constexpr int kBwdWaveBytes = 12;           // LDS bytes per vertex and destination
+constexpr int kBwdWavePad = 16;             // words between two waves' arrays (LDS banks)
 
 __device__ __forceinline__ void wave_sync_bwd() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__host__ __device__ __forceinline__ int64_t bwd_wave_stride_words(int n_cap) {
+    return (int64_t)(kBwdWaveBytes / 4) * n_cap + kBwdWavePad;
 }
 
 __global__ __launch_bounds__(256) void backward_wave_kernel(
@@ -185,72 +194,87 @@ __global__ __launch_bounds__(256) void backward_wave_kernel(
         }
     }
     if (n <= 1) return;
-    const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int t = (int)threadIdx.x, w = t >> 6, lane = t & 63;
     // workgroups are dealt to the XCDs round-robin: each XCD gets a run of
     // neighbouring destinations, whose columns share cache lines
     const int per = (int)(gridDim.x / 8);
     const int grp = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-    const int j = grp * 4 + w;
-    if (j >= n) return;                     // the whole wave; no workgroup barrier follows
-    // this wave's arrays: cnt and S (n_cap 32-bit words each), then par and
-    // q (n_cap 16-bit entries each)
-    int *cnt = bwd_lds + (int64_t)w * (kBwdWaveBytes / 4) * n_cap;
-    float *S = reinterpret_cast<float *>(cnt + n_cap);
-    int16_t *par = reinterpret_cast<int16_t *>(S + n_cap);
-    int16_t *q = par + n_cap;
-    int &tail = s_tail[w];
+    const int j0 = grp * 4;
+    if (j0 >= n) return;                    // the whole workgroup; no barrier follows
+    const int64_t stride = bwd_wave_stride_words(n_cap);
     const float *Gg = G + base;
     const int32_t *Ng = NX + base;
     float *dWg = dW + base;
-    if (lane == 0) tail = 0;
+
+    // ---- columns j0 .. j0+3 into the four waves' arrays: thread t takes
+    // column c = t % 4 of rows r, r + 64, ... (r = t / 4)
+    const int c = t & 3, r = t >> 2, jc = j0 + c;
+    int *cnt_c = bwd_lds + c * stride;
+    float *S_c = reinterpret_cast<float *>(cnt_c + n_cap);
+    int16_t *par_c = reinterpret_cast<int16_t *>(S_c + n_cap);
+    if (t < 4) s_tail[t] = 0;
     for (int u0 = 0; u0 < n; u0 += 8 * 64) {
         int v[8];
         float g[8];
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
-            const int u = u0 + 64 * m + lane;
-            const int64_t o = (int64_t)(u < n ? u : 0) * ld + j;
+            const int u = u0 + 64 * m + r;
+            const int64_t o = (u < n && jc < n) ? (int64_t)u * ld + jc : 0;
             v[m] = Ng[o];
             g[m] = Gg[o];
         }
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
-            const int u = u0 + 64 * m + lane;
-            if (u < n) {
-                const bool on = u != j && v[m] >= 0 && v[m] < n;
-                par[u] = (int16_t)(on ? v[m] : -1);
-                S[u] = on ? g[m] : 0.0f;
-                cnt[u] = 0;
+            const int u = u0 + 64 * m + r;
+            if (u < n && jc < n) {
+                const bool on = u != jc && v[m] >= 0 && v[m] < n;
+                par_c[u] = (int16_t)(on ? v[m] : -1);
+                S_c[u] = on ? g[m] : 0.0f;
+                cnt_c[u] = 0;
             }
         }
     }
-    wave_sync_bwd();
-    for (int u = lane; u < n; u += 64) {
-        const int v = par[u];
-        if (v >= 0 && v != j) atomicAdd(&cnt[v], 1);
-    }
-    wave_sync_bwd();
-    for (int u = lane; u < n; u += 64)
-        if (par[u] >= 0 && cnt[u] == 0) q[atomicAdd(&tail, 1)] = (int16_t)u;
-    int head = 0;
-    for (;;) {
-        wave_sync_bwd();
-        const int end = tail;
-        if (head >= end) break;
-        for (int x = head + lane; x < end; x += 64) {
-            const int u = q[x];
+    __syncthreads();
+
+    // ---- this wave's tree (destination j)
+    const int j = j0 + w;
+    if (j < n) {
+        int *cnt = bwd_lds + w * stride;
+        float *S = reinterpret_cast<float *>(cnt + n_cap);
+        int16_t *par = reinterpret_cast<int16_t *>(S + n_cap);
+        int16_t *q = par + n_cap;
+        int &tail = s_tail[w];
+        for (int u = lane; u < n; u += 64) {
             const int v = par[u];
-            const float sv = S[u];
-            cnt[u] = -1;                                      // processed
-            if (v != j) {
-                atomicAdd(&S[v], sv);
-                if (atomicSub(&cnt[v], 1) == 1) q[atomicAdd(&tail, 1)] = (int16_t)v;
-            }
+            if (v >= 0 && v != j) atomicAdd(&cnt[v], 1);
         }
-        head = end;
+        wave_sync_bwd();
+        for (int u = lane; u < n; u += 64)
+            if (par[u] >= 0 && cnt[u] == 0) q[atomicAdd(&tail, 1)] = (int16_t)u;
+        int head = 0;
+        for (;;) {
+            wave_sync_bwd();
+            const int end = tail;
+            if (head >= end) break;
+            for (int x = head + lane; x < end; x += 64) {
+                const int u = q[x];
+                const int v = par[u];
+                const float sv = S[u];
+                cnt[u] = -1;                                      // processed
+                if (v != j) {
+                    atomicAdd(&S[v], sv);
+                    if (atomicSub(&cnt[v], 1) == 1) q[atomicAdd(&tail, 1)] = (int16_t)v;
+                }
+            }
+            head = end;
+        }
     }
-    wave_sync_bwd();
-    for (int u = lane; u < n; u += 64) dWg[(int64_t)u * ld + j] = cnt[u] == -1 ? S[u] : 0.0f;
+    __syncthreads();
+
+    // ---- the four columns of subtree sums back, row segments together
+    if (jc < n) {
+        for (int u = r; u < n; u += 64) dWg[(int64_t)u * ld + jc] = cnt_c[u] == -1 ? S_c[u] : 0.0f;
+    }
 }
 
 // Second pass: row u of every graph.  T[u][j] = S_j(u) (the first pass's
@@ -327,7 +351,7 @@ hipError_t launch_backward(const BackwardPlan &b) {
     if (b.n_cap <= kBwdWaveMaxN) {
         const int groups = (b.n_cap + 3) / 4;
         const unsigned gx = (unsigned)(8 * ((groups + 7) / 8));
-        const size_t lds = (size_t)4 * kBwdWaveBytes * b.n_cap;
+        const size_t lds = (size_t)4 * 4 * bwd_wave_stride_words(b.n_cap);
         hipLaunchKernelGGL(backward_wave_kernel, dim3(gx, graphs), dim3(256), lds, b.stream, b.G, b.NX, b.dW, b.n,
                            b.ld, b.off, b.nv, b.n_cap, b.err);
     } else if (b.n_cap <= kBackwardLdsMaxN) {
