@@ -358,6 +358,9 @@ __device__ __forceinline__ void closure_block(U *__restrict__ D, int32_t *__rest
                                               Phase1Smem<U, S, false> &sm) {
     constexpr int TX = NT / 16, MR = S / 16, MC = S / TX;
     static_assert(MR * 16 == S && MC * TX == S && MR <= 8 && MC <= 8, "patch of at most 8 x 8");
+    // The closure is a chain of barrier steps while the workgroup it shares
+    // a CU with usually runs tiles: its waves issue first while it lasts.
+    __builtin_amdgcn_s_setprio(2);
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));
     const int tx = t % TX, ty = t / TX;
@@ -450,6 +453,7 @@ __device__ __forceinline__ void closure_block(U *__restrict__ D, int32_t *__rest
             }
         }
     }
+    __builtin_amdgcn_s_setprio(0);
 }
 
 // ---------------------------------------------------- phases 2 and 3
