@@ -626,32 +626,39 @@ __device__ __forceinline__ void minplus_tile_impl(U *__restrict__ D, int32_t *__
     // an opaque thread index (see phase1_block)
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));
-    // Thread -> patch.  The eager variant gives each wave 16 x 4 threads: one
-    // 64-column half of the tile and 16 rows of each row half, so that a wave
-    // whose columns, or rows, all lie past a ragged tile's edge has nothing
-    // to relax; the other variants keep 32 x 2 threads per wave.
-    int tx, ty;
-    if constexpr (ARGMIN == 1 && NT == 512) {
-        const int w = t >> 6, l = t & 63;
-        tx = (w & 1) * 16 + (l & 15);
-        ty = (w >> 1) * 4 + (l >> 4);
-    } else {
-        tx = t % G::txn;
-        ty = t / G::txn;
-    }
     const int64_t b0 = (int64_t)K * BS;
     const int bk = (int)imin64((int64_t)BS, n - b0);
     const int64_t b1 = b0 + bk;
     // number of valid rows / columns of C (and of A's rows, B's columns)
     const int rows_valid = (mode == 1) ? bk : (int)imin64(kTile, n - row0);
     const int cols_valid = (mode == 2) ? bk : (int)imin64(kTile, n - col0);
-    // eager variant: this wave's columns (64 w&1 .. +63) or rows (16 (w>>1)
-    // .. +15 in each half) all invalid -- it stages operands and joins the
-    // barriers, and skips the relaxations
+    // Thread -> patch.  The eager variant gives each wave a block of the tile
+    // so that a wave whose columns, or rows, all lie past a ragged tile's edge
+    // has nothing to relax (it stages operands and joins the barriers, and
+    // skips the relaxations).  Of two layouts the tile takes the one with
+    // fewer waves left working: 16 x 4 threads per wave (a 64-column half,
+    // 16 rows of each 64-row half) or 8 x 8 (a 32-column quarter, 32 rows of
+    // each half).  The other variants keep 32 x 2 threads per wave.
+    int tx, ty;
     bool idle_wave = false;
     if constexpr (ARGMIN == 1 && NT == 512) {
-        const int w = __builtin_amdgcn_readfirstlane(t >> 6);
-        idle_wave = (w & 1) * 64 >= cols_valid || (w >> 1) * 16 >= rows_valid;
+        const int ca = min(2, (cols_valid + 63) / 64), ra = min(4, (rows_valid + 15) / 16);
+        const int cb = min(4, (cols_valid + 31) / 32), rb = min(2, (rows_valid + 31) / 32);
+        const bool quarters = cb * rb < ca * ra;      // uniform
+        const int w = t >> 6, l = t & 63;
+        const int ws = __builtin_amdgcn_readfirstlane(w);
+        if (quarters) {
+            tx = (w & 3) * 8 + (l & 7);
+            ty = (w >> 2) * 8 + (l >> 3);
+            idle_wave = (ws & 3) * 32 >= cols_valid || (ws >> 2) * 32 >= rows_valid;
+        } else {
+            tx = (w & 1) * 16 + (l & 15);
+            ty = (w >> 1) * 4 + (l >> 4);
+            idle_wave = (ws & 1) * 64 >= cols_valid || (ws >> 1) * 16 >= rows_valid;
+        }
+    } else {
+        tx = t % G::txn;
+        ty = t / G::txn;
     }
     constexpr bool use_vec = VEC;
     constexpr bool PACKABLE = ARGMIN == 2 && std::is_same<U, uint32_t>::value;
